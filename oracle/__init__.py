@@ -1,0 +1,18 @@
+"""Plain CPU FP64 oracle for the multi-species fast Fourier spectral collision operator.
+
+TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU-baseline leg
+of the benchmark import this package; the product library never does.  It shares
+no code with the HIP path: the only common module is ``synth`` (seeded inputs).
+
+Contents, each following the paper (Jaiswal, Alexeenko & Hu, "A discontinuous
+Galerkin fast spectral method for the multi-species Boltzmann equation"):
+
+* ``params``      pair coefficients, VHS/VSS prefactor, Knudsen numbers, the
+                  truncation radius from the anti-aliasing condition (Secs. 2-4).
+* ``quadrature``  Gauss-Legendre radial rule, spherical designs (Sec. 4).
+* ``spectral``    Fourier coefficients, kernel mode F, loss weight G^-, the direct
+                  O(N^6) spectral sum, the fast sum, and the exact-sphere variant.
+* ``moments``     moments, the Maxwellian, the FP64 conservation projection.
+* ``bkw``         the Krook-Wu exact solution and its time derivative (Sec. 6.1).
+"""
+from . import params, quadrature, spectral, moments, bkw  # noqa: F401
