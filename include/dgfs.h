@@ -1,0 +1,150 @@
+/*
+ * dgfs.h -- C ABI of the MI355X (gfx950) multi-species fast Fourier spectral
+ * collision operator.
+ *
+ * The library evaluates, for a batch of independent spatial points ("nodes"),
+ *
+ *     Q^i(v) = sum_j Q^{ij}(f^i, f^j)(v),        i = 1..s,
+ *
+ * the right-hand side of the dimensionless multi-species Boltzmann equation
+ * (paper: Jaiswal, Alexeenko & Hu, Sec. 3, eq. NMBE), with each Q^{ij} computed by
+ * the fast spectral method of Sec. 4: Fourier series on [-L, L]^3 with N modes per
+ * dimension, a Gauss-Legendre rule of n_rho points on [0, R_ij] and an M-point
+ * spherical design for the gain term, and the loss term as one convolution.  The
+ * per-pair constant C_ij (Kn_ij^{-1} times the kernel constant of eq. NVSS) is an
+ * input, so any VHS kernel B_ij = C_ij |g|^{2(1-omega_ij)} is accepted (the fast
+ * algorithm does not depend on the kernel form: the remark after eq. NVSS).
+ *
+ * Conventions (shared by every entry point):
+ *   - Distribution functions and results are laid out [batch][s][N][N][N], the last
+ *     (z) index fastest, real, in the plan's precision (float or double).
+ *   - Species i is sampled at v_n = -L + n 2L/N, n = 0..N-1, per dimension.
+ *   - Mode k of the truncated series runs over [-N/2, N/2-1]^3 (Sec. 4); the DFT
+ *     index N/2 stands for the mode -N/2.  The sum over l + m = k in eq. (sum) is
+ *     taken modulo N (circular), which is what its FFT evaluation computes.
+ *   - R_ij = 2 S with S the largest support radius allowed by the anti-aliasing
+ *     condition (Sec. 4, eq. domain) for both orderings of the pair.
+ *   - Spherical designs: M = 6 (octahedron), 12 (icosahedron), 24 (the orbit of
+ *     one point under the 24 rotations of the cube that forms a 7-design).
+ *
+ * Memory and threading:
+ *   - Every device pointer is owned by the caller.  The plan owns its tables,
+ *     allocated on the current device in dgfs_plan_create and freed in
+ *     dgfs_plan_destroy; it copies every host array of dgfs_problem.
+ *   - Compute entry points are asynchronous on the given HIP stream (a
+ *     hipStream_t passed as void*; NULL is the default stream) and never allocate.
+ *   - A plan is immutable after creation: concurrent calls on different streams with
+ *     different workspaces are allowed.
+ *   - Errors are returned as dgfs_status; dgfs_last_error() gives a thread-local text.
+ */
+#ifndef DGFS_H
+#define DGFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DGFS_OK = 0,
+    DGFS_EINVAL = -1,        /* invalid argument (message in dgfs_last_error) */
+    DGFS_EUNSUPPORTED = -2,  /* valid but not implemented (e.g. an N without kernels) */
+    DGFS_ENOMEM = -3,        /* device allocation failed, or workspace too small */
+    DGFS_EDEVICE = -4        /* a HIP call or kernel launch failed */
+} dgfs_status;
+
+enum { DGFS_FP32 = 0, DGFS_FP64 = 1 };
+
+/* Collision kernel of one ordered pair: B_ij = prefactor * |g|^{2(1-omega)}
+ * (VHS, Sec. 2 eq. VSS with alpha = 1).  omega in [0.5, 1]; alpha must be 1
+ * (the VSS case alpha > 1 returns DGFS_EUNSUPPORTED).  prefactor > 0. */
+typedef struct {
+    double omega;
+    double alpha;
+    double prefactor;
+} dgfs_pair_kernel;
+
+typedef struct {
+    int32_t s;                       /* number of species, 1..8 */
+    const double* mass;              /* [s] nondimensional masses, > 0 */
+    double L;                        /* half-width of the velocity box [-L, L]^3, > 0 */
+    const double* L_species;         /* NULL, or [s] per-species half-widths (species-specific
+                                        grids; only the common-grid case is implemented:
+                                        a non-NULL array with unequal entries returns
+                                        DGFS_EUNSUPPORTED) */
+    int32_t N;                       /* modes per dimension: 16, 24, 32 or 48 */
+    int32_t M;                       /* spherical design size: 6, 12 or 24 */
+    int32_t n_rho;                   /* radial Gauss-Legendre points, 1..128 */
+    const dgfs_pair_kernel* kernel;  /* [s*s], row-major (i, j); must be symmetric:
+                                        kernel[i*s+j] == kernel[j*s+i] (the cross-species
+                                        conservation of Sec. 2, eq. consv, needs it) */
+    int32_t precision;               /* DGFS_FP32 or DGFS_FP64 */
+} dgfs_problem;
+
+typedef struct dgfs_plan dgfs_plan;
+
+/* Host-side check of a problem description; no device is touched.
+ * Returns DGFS_OK, DGFS_EINVAL or DGFS_EUNSUPPORTED. */
+dgfs_status dgfs_check_problem(const dgfs_problem* problem);
+
+/* Precompute (Sec. 4, "precompute F and G- up to a high accuracy"): quadrature,
+ * designs, radial kernel tables F^{ij}(|k|, rho_q), loss weights G^{ij-}(|m|) and
+ * phase tables, in FP64 on the host, stored in the plan precision on the current
+ * device.  *out is set only on DGFS_OK. */
+dgfs_status dgfs_plan_create(const dgfs_problem* problem, dgfs_plan** out);
+
+void dgfs_plan_destroy(dgfs_plan* plan);
+
+/* Bytes of device workspace dgfs_collide/dgfs_collide_pairs need for `batch` nodes
+ * processed in one pass.  A smaller workspace (at least the one-node size) makes the
+ * call process the batch in slices. */
+dgfs_status dgfs_workspace_size(const dgfs_plan* plan, int64_t batch, size_t* bytes);
+
+/* Q[b][i] = sum_j Q^{ij}(f[b][i], f[b][j]) for b < batch.
+ * f, Q: device arrays [batch][s][N^3] of the plan precision; f and Q must not overlap.
+ * workspace: device memory, 256-byte aligned, ws_bytes >= dgfs_workspace_size(plan, 1). */
+dgfs_status dgfs_collide(const dgfs_plan* plan, const void* f, void* Q, int64_t batch,
+                         void* workspace, size_t ws_bytes, void* stream);
+
+/* Same result as dgfs_collide, for measurement: HIP events are recorded on `stream`
+ * around each stage, the call waits for the work to finish, and stage_ms[0..4]
+ * receives the summed durations (over batch slices) of: the forward transform of f,
+ * the gain kernel (the sigma/rho loop of Sec. 4), the radial-sum and loss-spectrum
+ * kernel, the inverse transforms, and the final combination.  Synchronous. */
+dgfs_status dgfs_collide_timed(const dgfs_plan* plan, const void* f, void* Q, int64_t batch,
+                               void* workspace, size_t ws_bytes, void* stream, float* stage_ms);
+
+/* Per ordered pair: Q[b][i][j] = Q^{ij}(f[b][i], f[b][j]), Q shaped [batch][s][s][N^3]. */
+dgfs_status dgfs_collide_pairs(const dgfs_plan* plan, const void* f, void* Q, int64_t batch,
+                               void* workspace, size_t ws_bytes, void* stream);
+
+/* FP64 conservation correction (least-squares projection onto the collision
+ * invariants of Sec. 2, eq. consv): with A the (s+4) x (s N^3) matrix of species
+ * numbers, total momentum and total energy (rectangle rule, weight h^3 and m_i),
+ *     Q_out = Q_raw - A^T (A A^T)^{-1} A Q_raw      per node, in FP64.
+ * Q_raw: device [batch][s][N^3] in the plan precision; Q_out: device double array of
+ * the same shape (may alias Q_raw only when the plan precision is FP64). */
+dgfs_status dgfs_conserve(const dgfs_plan* plan, const void* Q_raw, double* Q_out, int64_t batch,
+                          void* stream);
+
+/* Host-side view of the precomputed quantities of ordered pair (i, j), for tests:
+ *   info[0..5] = a, b, gamma, C_ij, R_ij, number of phase directions used;
+ *   rho, w_rho: [n_rho] radial nodes and weights on [0, R_ij];
+ *   loss: [3 (N/2)^2 + 1] G^{ij-} as a function of |m|^2 (no 1/N^3 factor).
+ * Any output pointer may be NULL.  No device is touched. */
+dgfs_status dgfs_pair_tables(const dgfs_problem* problem, int32_t i, int32_t j, double* info,
+                             double* rho, double* w_rho, double* loss);
+
+/* Host-side copy of the M-point design used by the plan, [M][3]. */
+dgfs_status dgfs_design(int32_t M, double* sigma);
+
+const char* dgfs_status_string(dgfs_status status);
+const char* dgfs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGFS_H */

@@ -35,6 +35,7 @@ Three evaluations of the same discretised operator are provided:
 """
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -43,6 +44,9 @@ import scipy.special
 
 from . import params as P
 from . import quadrature as Qd
+
+# FFT worker threads: the host's CPU share (OMP_NUM_THREADS when set).
+WORKERS = max(1, min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS") or (os.cpu_count() or 1))))
 
 
 # --------------------------------------------------------------------------- modes
@@ -200,21 +204,21 @@ def _coefficients_fft(f: np.ndarray) -> np.ndarray:
     """f_hat_k via the FFT: the grid starts at -L, which contributes (-1)^{k1+k2+k3}."""
     N = f.shape[0]
     s = (-1.0) ** np.add.outer(np.add.outer(np.arange(N), np.arange(N)), np.arange(N))
-    return s * scipy.fft.fftn(f, workers=-1) / N ** 3
+    return s * scipy.fft.fftn(f, workers=WORKERS) / N ** 3
 
 
 def _synthesize_fft(Qhat: np.ndarray) -> np.ndarray:
     N = Qhat.shape[0]
     s = (-1.0) ** np.add.outer(np.add.outer(np.arange(N), np.arange(N)), np.arange(N))
-    return scipy.fft.ifftn(s * Qhat, workers=-1) * N ** 3
+    return scipy.fft.ifftn(s * Qhat, workers=WORKERS) * N ** 3
 
 
 def circular_convolution(X: np.ndarray, Y: np.ndarray) -> np.ndarray:
     """sum_{l+m = k (mod N)} X_l Y_m for arrays indexed by DFT index, by FFT."""
     N = X.shape[0]
-    x = scipy.fft.ifftn(X, workers=-1)
-    y = scipy.fft.ifftn(Y, workers=-1)
-    return scipy.fft.fftn(x * y, workers=-1) * N ** 3
+    x = scipy.fft.ifftn(X, workers=WORKERS)
+    y = scipy.fft.ifftn(Y, workers=WORKERS)
+    return scipy.fft.fftn(x * y, workers=WORKERS) * N ** 3
 
 
 def collide_pair_fast(fi: np.ndarray, fj: np.ndarray, pr: Pair) -> np.ndarray:

@@ -1,0 +1,14 @@
+"""MI355X (gfx950) multi-species fast Fourier spectral collision operator.
+
+The library (libdgfs.so, C ABI in include/dgfs.h) evaluates
+Q^i = sum_j Q^{ij}(f^i, f^j) for a batch of independent spatial points with hand-written
+HIP kernels; this package is its thin Python binding.
+"""
+from .collision import (  # noqa: F401
+    CollisionPlan,
+    check_problem,
+    design,
+    pair_tables,
+    vhs_kernel,
+    vhs_prefactor,
+)

@@ -1,0 +1,528 @@
+// C ABI of the collision library: validation, host-side precomputation (FP64),
+// upload of the plan tables, workspace slicing and launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dgfs.h"
+#include "plan.hpp"
+#include "precompute.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+dgfs_status fail(dgfs_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+int signed_mode(int j, int N) { return j < N / 2 ? j : j - N; }
+
+bool n_supported(int N) { return N == 16 || N == 24 || N == 32 || N == 48; }
+
+dgfs_status check(const dgfs_problem* p) {
+    if (!p) return fail(DGFS_EINVAL, "problem is NULL");
+    if (p->s < 1 || p->s > 8) return fail(DGFS_EINVAL, "s must be in [1, 8]");
+    if (!p->mass || !p->kernel) return fail(DGFS_EINVAL, "mass and kernel arrays are required");
+    for (int i = 0; i < p->s; ++i)
+        if (!(p->mass[i] > 0.0) || !std::isfinite(p->mass[i])) return fail(DGFS_EINVAL, "masses must be positive");
+    if (!(p->L > 0.0) || !std::isfinite(p->L)) return fail(DGFS_EINVAL, "L must be positive");
+    if (p->N < 4 || p->N % 2 != 0) return fail(DGFS_EINVAL, "N must be even and >= 4");
+    if (p->M != 6 && p->M != 12 && p->M != 24) return fail(DGFS_EINVAL, "no spherical design for this M (6, 12, 24)");
+    if (p->n_rho < 1 || p->n_rho > 128) return fail(DGFS_EINVAL, "n_rho must be in [1, 128]");
+    if (p->precision != DGFS_FP32 && p->precision != DGFS_FP64) return fail(DGFS_EINVAL, "unknown precision");
+    for (int i = 0; i < p->s; ++i)
+        for (int j = 0; j < p->s; ++j) {
+            const dgfs_pair_kernel& k = p->kernel[i * p->s + j];
+            const dgfs_pair_kernel& t = p->kernel[j * p->s + i];
+            if (!(k.omega >= 0.5 && k.omega <= 1.0)) return fail(DGFS_EINVAL, "omega must be in [0.5, 1]");
+            if (!(k.alpha >= 1.0 && k.alpha <= 2.0)) return fail(DGFS_EINVAL, "alpha must be in [1, 2]");
+            if (!(k.prefactor > 0.0) || !std::isfinite(k.prefactor))
+                return fail(DGFS_EINVAL, "prefactor must be positive");
+            if (k.omega != t.omega || k.alpha != t.alpha || k.prefactor != t.prefactor)
+                return fail(DGFS_EINVAL, "kernel must be symmetric in (i, j)");
+        }
+    if (p->L_species)
+        for (int i = 0; i < p->s; ++i) {
+            if (!(p->L_species[i] > 0.0)) return fail(DGFS_EINVAL, "L_species must be positive");
+            if (p->L_species[i] != p->L)
+                return fail(DGFS_EUNSUPPORTED, "species-specific grids are not implemented");
+        }
+    for (int i = 0; i < p->s * p->s; ++i)
+        if (p->kernel[i].alpha != 1.0) return fail(DGFS_EUNSUPPORTED, "VSS kernels (alpha > 1) are not implemented");
+    if (!n_supported(p->N)) return fail(DGFS_EUNSUPPORTED, "N must be 16, 24, 32 or 48");
+    dgfs::GainGeometry g;
+    if (!dgfs::gain_geometry(p->N, p->precision, &g))
+        return fail(DGFS_EUNSUPPORTED, "no kernel for this N at this precision");
+    return DGFS_OK;
+}
+
+dgfs::PairParams pair_params(const dgfs_problem* p, int i, int j) {
+    dgfs::PairParams pp;
+    const double mi = p->mass[i], mj = p->mass[j];
+    pp.a = mj / (mi + mj);
+    pp.b = mi / (mi + mj);
+    pp.gamma = 2.0 * (1.0 - p->kernel[i * p->s + j].omega);
+    pp.C = p->kernel[i * p->s + j].prefactor;
+    pp.R = dgfs::pre::truncation_radius(p->L, mi, mj);
+    dgfs::pre::gauss_legendre(p->n_rho, pp.R, pp.rho, pp.wrho);
+    return pp;
+}
+
+// Symmetric positive definite solve by Gauss-Jordan with partial pivoting: inverse of A (n x n).
+bool invert(std::vector<double> A, int n, std::vector<double>& inv) {
+    inv.assign(n * n, 0.0);
+    for (int i = 0; i < n; ++i) inv[i * n + i] = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+        if (A[piv * n + c] == 0.0) return false;
+        for (int k = 0; k < n; ++k) {
+            std::swap(A[c * n + k], A[piv * n + k]);
+            std::swap(inv[c * n + k], inv[piv * n + k]);
+        }
+        const double d = A[c * n + c];
+        for (int k = 0; k < n; ++k) {
+            A[c * n + k] /= d;
+            inv[c * n + k] /= d;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const double fct = A[r * n + c];
+            if (fct == 0.0) continue;
+            for (int k = 0; k < n; ++k) {
+                A[r * n + k] -= fct * A[c * n + k];
+                inv[r * n + k] -= fct * inv[c * n + k];
+            }
+        }
+    }
+    return true;
+}
+
+template <typename T>
+void push_real(std::vector<char>& blob, size_t& off, const std::vector<double>& v) {
+    off = (blob.size() + 255) & ~size_t(255);
+    blob.resize(off + v.size() * sizeof(T));
+    T* dst = reinterpret_cast<T*>(blob.data() + off);
+    for (size_t k = 0; k < v.size(); ++k) dst[k] = T(v[k]);
+}
+
+template <typename T>
+void push_cplx(std::vector<char>& blob, size_t& off, const std::vector<std::complex<double>>& v) {
+    off = (blob.size() + 255) & ~size_t(255);
+    blob.resize(off + v.size() * 2 * sizeof(T));
+    T* dst = reinterpret_cast<T*>(blob.data() + off);
+    for (size_t k = 0; k < v.size(); ++k) {
+        dst[2 * k] = T(v[k].real());
+        dst[2 * k + 1] = T(v[k].imag());
+    }
+}
+
+void push_int(std::vector<char>& blob, size_t& off, const std::vector<int>& v) {
+    off = (blob.size() + 255) & ~size_t(255);
+    blob.resize(off + v.size() * sizeof(int));
+    std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(int));
+}
+
+void push_double(std::vector<char>& blob, size_t& off, const std::vector<double>& v) { push_real<double>(blob, off, v); }
+
+// Build every host table and lay it out in one byte blob for the device.
+template <typename T>
+void build_tables(dgfs_plan& P, std::vector<char>& blob) {
+    const int N = P.N, s = P.s, nrho = P.nrho, CH = P.geo.CH, NP = N / CH;
+    const double L = P.L;
+    // ---------------- phase tables [dirs][nrho][2][CH][N] and [dirs][nrho][2][2][N]
+    std::vector<std::complex<double>> kx(size_t(P.total_dirs) * nrho * 2 * CH * N);
+    std::vector<std::complex<double>> yz(size_t(P.total_dirs) * nrho * 2 * 2 * N);
+    std::vector<int> cls;
+    std::vector<double> wdir;
+    std::vector<int> design_index;  // global direction -> design point
+    for (const auto& c : P.classes) {
+        cls.insert(cls.end(), {c.i, c.j, c.ndir, c.dir_offset});
+        wdir.push_back(c.weight);
+    }
+    // directions per class (rebuilt the same way as in plan creation)
+    for (size_t k = 0; k < P.classes.size(); ++k) {
+        const auto& c = P.classes[k];
+        const dgfs::PairParams& pp = P.pair[c.i * s + c.j];
+        std::vector<int> dirs;
+        if (c.i == c.j && P.antipodal) {
+            for (int p = 0; p < P.M; ++p) {
+                int anti = -1;
+                for (int q = 0; q < P.M; ++q) {
+                    double d = 0;
+                    for (int e = 0; e < 3; ++e) d += std::fabs(P.sigma[3 * p + e] + P.sigma[3 * q + e]);
+                    if (d < 1e-12) anti = q;
+                }
+                if (anti > p) dirs.push_back(p);
+            }
+        } else {
+            for (int p = 0; p < P.M; ++p) dirs.push_back(p);
+        }
+        for (int d = 0; d < c.ndir; ++d) {
+            const int gd = c.dir_offset + d;
+            const double* sg = &P.sigma[3 * dirs[d]];
+            for (int q = 0; q < nrho; ++q) {
+                for (int fld = 0; fld < 2; ++fld) {
+                    const double sgn = fld == 0 ? 1.0 : -1.0;
+                    const double coef = fld == 0 ? c.a : c.b;
+                    const double th[3] = {sgn * kPi * pp.rho[q] * coef * sg[0] / L,
+                                          sgn * kPi * pp.rho[q] * coef * sg[1] / L,
+                                          sgn * kPi * pp.rho[q] * coef * sg[2] / L};
+                    const size_t base = (size_t(gd) * nrho + q) * 2 + fld;
+                    for (int cc = 0; cc < CH; ++cc)
+                        for (int t = 0; t < CH; ++t)
+                            for (int l = 0; l < NP; ++l) {
+                                const int jx = l + t * NP;
+                                const double ang = th[0] * signed_mode(jx, N) +
+                                                   2.0 * kPi * (double(t * cc) / CH + double(l * cc) / N);
+                                kx[(base * CH + cc) * N + jx] = std::polar(1.0, ang);
+                            }
+                    for (int jj = 0; jj < N; ++jj) {
+                        yz[(base * 2 + 0) * N + jj] = std::polar(1.0, th[1] * signed_mode(jj, N));
+                        yz[(base * 2 + 1) * N + jj] = std::polar(1.0, th[2] * signed_mode(jj, N));
+                    }
+                }
+            }
+        }
+    }
+    push_cplx<T>(blob, P.off_kx, kx);
+    push_cplx<T>(blob, P.off_yz, yz);
+    push_int(blob, P.off_cls, cls);
+    push_real<T>(blob, P.off_wdir, wdir);
+
+    // ---------------- F tables per (class, target) and G tables per ordered pair
+    const int K2 = P.K2;
+    const double n3 = double(N) * N * N;
+    std::vector<double> F;
+    std::vector<std::vector<int>> ftab(P.classes.size(), std::vector<int>(s, -1));
+    int nft = 0;
+    for (size_t k = 0; k < P.classes.size(); ++k) {
+        const auto& c = P.classes[k];
+        std::vector<int> targets = {c.i};
+        if (c.i != c.j && P.antipodal) targets.push_back(c.j);
+        for (int tg : targets) {
+            const int other = tg == c.i ? c.j : c.i;
+            const dgfs::PairParams& pp = P.pair[tg * s + other];
+            for (int q = 0; q < nrho; ++q)
+                for (int k2 = 0; k2 < K2; ++k2)
+                    F.push_back(pp.wrho[q] *
+                                dgfs::pre::kernel_mode(std::sqrt(double(k2)), pp.rho[q], pp.a, pp.gamma, pp.C, L) / n3);
+            ftab[k][tg] = nft++;
+        }
+    }
+    P.nftab = nft;
+    std::vector<double> G(size_t(s) * s * K2);
+    for (int i = 0; i < s; ++i)
+        for (int j = 0; j < s; ++j) {
+            const dgfs::PairParams& pp = P.pair[i * s + j];
+            if (j < i) {  // G- depends on (C, gamma, R), all symmetric in (i, j)
+                std::copy_n(&G[size_t(j * s + i) * K2], K2, &G[size_t(i * s + j) * K2]);
+                continue;
+            }
+            for (int k2 = 0; k2 < K2; ++k2)
+                G[size_t(i * s + j) * K2 + k2] = dgfs::pre::loss_weight(std::sqrt(double(k2)), pp.R, pp.gamma, pp.C, L);
+        }
+    P.ngtab = s * s;
+    push_real<T>(blob, P.off_F, F);
+    push_real<T>(blob, P.off_G, G);
+
+    // ---------------- chunk-combine twiddles e^{-2 pi i kx c / N}, [N][CH]
+    std::vector<std::complex<double>> tw(size_t(N) * CH);
+    for (int kxi = 0; kxi < N; ++kxi)
+        for (int cc = 0; cc < CH; ++cc) tw[kxi * CH + cc] = std::polar(1.0, -2.0 * kPi * double(kxi * cc % N) / N);
+    push_cplx<T>(blob, P.off_tw, tw);
+
+    // ---------------- slots: summed (one per species) and per ordered pair
+    auto cls_of = [&](int i, int j) {
+        for (size_t k = 0; k < P.classes.size(); ++k) {
+            const auto& c = P.classes[k];
+            if (c.i == i && c.j == j) return int(k);
+            if (P.antipodal && c.i == j && c.j == i) return int(k);
+        }
+        return -1;
+    };
+    {
+        dgfs::SlotSet& S = P.sum_slots;
+        S = dgfs::SlotSet();
+        S.nslots = s;
+        for (int i = 0; i < s; ++i) {
+            const int g0 = int(S.gterms.size() / 2), l0 = int(S.lterms.size() / 2);
+            for (size_t k = 0; k < P.classes.size(); ++k)
+                if (ftab[k][i] >= 0) S.gterms.insert(S.gterms.end(), {int(k), ftab[k][i]});
+            for (int j = 0; j < s; ++j) S.lterms.insert(S.lterms.end(), {j, i * s + j});
+            S.slots.insert(S.slots.end(), {i, g0, int(S.gterms.size() / 2) - g0, l0, int(S.lterms.size() / 2) - l0});
+        }
+        push_int(blob, S.off_slots, S.slots);
+        push_int(blob, S.off_gterms, S.gterms);
+        push_int(blob, S.off_lterms, S.lterms);
+    }
+    {
+        dgfs::SlotSet& S = P.pair_slots;
+        S = dgfs::SlotSet();
+        S.nslots = s * s;
+        for (int i = 0; i < s; ++i)
+            for (int j = 0; j < s; ++j) {
+                const int k = cls_of(i, j);
+                const int g0 = int(S.gterms.size() / 2), l0 = int(S.lterms.size() / 2);
+                S.gterms.insert(S.gterms.end(), {k, ftab[k][i]});
+                S.lterms.insert(S.lterms.end(), {j, i * s + j});
+                S.slots.insert(S.slots.end(), {i, g0, 1, l0, 1});
+            }
+        push_int(blob, S.off_slots, S.slots);
+        push_int(blob, S.off_gterms, S.gterms);
+        push_int(blob, S.off_lterms, S.lterms);
+    }
+
+    // ---------------- conservation: inverse Gram matrix of the s+4 invariants, masses
+    {
+        const int nr = s + 4;
+        const double h = 2.0 * L / N, h6 = std::pow(h, 6);
+        double S1 = 0, S2 = 0, S3 = 0, S4 = 0;
+        for (int n = 0; n < N; ++n) {
+            const double v = -L + n * h;
+            S1 += v;
+            S2 += v * v;
+            S3 += v * v * v;
+            S4 += v * v * v * v;
+        }
+        const double Nd = N;
+        double msum2 = 0;
+        for (int i = 0; i < s; ++i) msum2 += P.mass[i] * P.mass[i];
+        std::vector<double> Gm(nr * nr, 0.0);
+        for (int i = 0; i < s; ++i) {
+            Gm[i * nr + i] = h6 * Nd * Nd * Nd;
+            for (int d = 0; d < 3; ++d) Gm[i * nr + s + d] = Gm[(s + d) * nr + i] = P.mass[i] * h6 * Nd * Nd * S1;
+            Gm[i * nr + s + 3] = Gm[(s + 3) * nr + i] = P.mass[i] * h6 * 3.0 * Nd * Nd * S2;
+        }
+        for (int d = 0; d < 3; ++d)
+            for (int e = 0; e < 3; ++e) Gm[(s + d) * nr + s + e] = msum2 * h6 * (d == e ? Nd * Nd * S2 : Nd * S1 * S1);
+        for (int d = 0; d < 3; ++d)
+            Gm[(s + d) * nr + s + 3] = Gm[(s + 3) * nr + s + d] = msum2 * h6 * (Nd * Nd * S3 + 2.0 * Nd * S1 * S2);
+        Gm[(s + 3) * nr + s + 3] = msum2 * h6 * (3.0 * Nd * Nd * S4 + 6.0 * Nd * S2 * S2);
+        std::vector<double> inv;
+        invert(Gm, nr, inv);
+        std::vector<double> pack = inv;
+        pack.insert(pack.end(), P.mass.begin(), P.mass.end());
+        push_double(blob, P.off_minv, pack);
+    }
+}
+
+}  // namespace
+
+size_t dgfs_plan::ws_per_node(bool pairs) const {
+    const size_t c = 2 * elem() * n3();
+    const int nslots = pairs ? s * s : s;
+    return c * (size_t(s) + classes.size() * size_t(nrho) + 2 * size_t(nslots));
+}
+
+extern "C" {
+
+dgfs_status dgfs_check_problem(const dgfs_problem* problem) { return check(problem); }
+
+dgfs_status dgfs_design(int32_t M, double* sigma) {
+    std::vector<double> pts;
+    if (!dgfs::pre::design(M, pts)) return fail(DGFS_EINVAL, "no spherical design for this M (6, 12, 24)");
+    if (sigma) std::copy(pts.begin(), pts.end(), sigma);
+    return DGFS_OK;
+}
+
+dgfs_status dgfs_pair_tables(const dgfs_problem* problem, int32_t i, int32_t j, double* info, double* rho,
+                             double* w_rho, double* loss) {
+    dgfs_status st = check(problem);
+    if (st == DGFS_EINVAL) return st;
+    if (i < 0 || j < 0 || i >= problem->s || j >= problem->s) return fail(DGFS_EINVAL, "pair index out of range");
+    dgfs::PairParams pp = pair_params(problem, i, j);
+    std::vector<double> pts;
+    dgfs::pre::design(problem->M, pts);
+    const bool anti = dgfs::pre::antipodal(pts);
+    if (info) {
+        info[0] = pp.a;
+        info[1] = pp.b;
+        info[2] = pp.gamma;
+        info[3] = pp.C;
+        info[4] = pp.R;
+        info[5] = (i == j && anti) ? problem->M / 2 : problem->M;
+    }
+    if (rho) std::copy(pp.rho.begin(), pp.rho.end(), rho);
+    if (w_rho) std::copy(pp.wrho.begin(), pp.wrho.end(), w_rho);
+    if (loss) {
+        const int K2 = 3 * (problem->N / 2) * (problem->N / 2) + 1;
+        for (int k2 = 0; k2 < K2; ++k2)
+            loss[k2] = dgfs::pre::loss_weight(std::sqrt(double(k2)), pp.R, pp.gamma, pp.C, problem->L);
+    }
+    return DGFS_OK;
+}
+
+dgfs_status dgfs_plan_create(const dgfs_problem* problem, dgfs_plan** out) {
+    if (!out) return fail(DGFS_EINVAL, "out is NULL");
+    dgfs_status st = check(problem);
+    if (st != DGFS_OK) return st;
+    auto* P = new dgfs_plan();
+    P->s = problem->s;
+    P->N = problem->N;
+    P->M = problem->M;
+    P->nrho = problem->n_rho;
+    P->precision = problem->precision;
+    P->L = problem->L;
+    P->mass.assign(problem->mass, problem->mass + problem->s);
+    dgfs::gain_geometry(P->N, P->precision, &P->geo);
+    dgfs::pre::design(P->M, P->sigma);
+    P->antipodal = dgfs::pre::antipodal(P->sigma);
+    P->K2 = 3 * (P->N / 2) * (P->N / 2) + 1;
+    for (int i = 0; i < P->s; ++i)
+        for (int j = 0; j < P->s; ++j) P->pair.push_back(pair_params(problem, i, j));
+    // gain classes
+    int off = 0;
+    const double w = 4.0 * kPi / P->M;
+    for (int i = 0; i < P->s; ++i)
+        for (int j = 0; j < P->s; ++j) {
+            if (P->antipodal && j < i) continue;
+            dgfs::GainClass c;
+            c.i = i;
+            c.j = j;
+            c.a = P->pair[i * P->s + j].a;
+            c.b = P->pair[i * P->s + j].b;
+            const bool half = P->antipodal && i == j;
+            c.ndir = half ? P->M / 2 : P->M;
+            c.weight = half ? 2.0 * w : w;
+            c.dir_offset = off;
+            off += c.ndir;
+            P->classes.push_back(c);
+        }
+    P->total_dirs = off;
+
+    std::vector<char> blob;
+    if (P->precision == DGFS_FP64) build_tables<double>(*P, blob);
+    else build_tables<float>(*P, blob);
+
+    if (hipGetDevice(&P->device) != hipSuccess) {
+        delete P;
+        return fail(DGFS_EDEVICE, "no HIP device");
+    }
+    P->dev_bytes = blob.size();
+    if (hipMalloc(&P->dev, P->dev_bytes) != hipSuccess) {
+        delete P;
+        return fail(DGFS_ENOMEM, "device allocation of the plan tables failed");
+    }
+    if (hipMemcpy(P->dev, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(P->dev);
+        delete P;
+        return fail(DGFS_EDEVICE, "upload of the plan tables failed");
+    }
+    *out = P;
+    return DGFS_OK;
+}
+
+void dgfs_plan_destroy(dgfs_plan* plan) {
+    if (!plan) return;
+    if (plan->dev) hipFree(plan->dev);
+    delete plan;
+}
+
+dgfs_status dgfs_workspace_size(const dgfs_plan* plan, int64_t batch, size_t* bytes) {
+    if (!plan || !bytes) return fail(DGFS_EINVAL, "plan and bytes are required");
+    if (batch < 1) return fail(DGFS_EINVAL, "batch must be >= 1");
+    // the pair-resolved mode needs the larger slot set; size for it
+    *bytes = plan->ws_per_node(true) * size_t(batch) + 4 * 256;
+    return DGFS_OK;
+}
+
+static dgfs_status collide_impl(const dgfs_plan* plan, const void* f, void* Q, int64_t batch, void* ws,
+                                size_t ws_bytes, void* stream, bool pairs, float* stage_ms) {
+    if (!plan) return fail(DGFS_EINVAL, "plan is NULL");
+    if (batch < 0) return fail(DGFS_EINVAL, "batch must be >= 0");
+    if (batch == 0) return DGFS_OK;
+    if (!f || !Q || !ws) return fail(DGFS_EINVAL, "f, Q and workspace are required");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(DGFS_EINVAL, "workspace must be 256-byte aligned");
+    const size_t per = plan->ws_per_node(pairs);
+    if (ws_bytes < per + 4 * 256) return fail(DGFS_ENOMEM, "workspace smaller than one node");
+    const int64_t slice = std::min<int64_t>(batch, int64_t((ws_bytes - 4 * 256) / per));
+    const int nslots = pairs ? plan->s * plan->s : plan->s;
+    const size_t in_stride = size_t(plan->s) * plan->n3() * plan->elem();
+    const size_t out_stride = size_t(nslots) * plan->n3() * plan->elem();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipEvent_t ev[6] = {};
+    if (stage_ms) {
+        for (int k = 0; k < 5; ++k) stage_ms[k] = 0.0f;
+        for (auto& e : ev)
+            if (hipEventCreate(&e) != hipSuccess) return fail(DGFS_EDEVICE, "hipEventCreate failed");
+    }
+    dgfs_status result = DGFS_OK;
+    for (int64_t b0 = 0; b0 < batch; b0 += slice) {
+        const int64_t nb = std::min(slice, batch - b0);
+        hipError_t e = dgfs::launch_collide(*plan, static_cast<const char*>(f) + b0 * in_stride,
+                                            static_cast<char*>(Q) + b0 * out_stride, nb, ws, pairs, st,
+                                            stage_ms ? ev : nullptr);
+        if (e != hipSuccess) {
+            result = fail(DGFS_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+            break;
+        }
+        if (stage_ms) {
+            if (hipEventSynchronize(ev[5]) != hipSuccess) {
+                result = fail(DGFS_EDEVICE, "hipEventSynchronize failed");
+                break;
+            }
+            for (int k = 0; k < 5; ++k) {
+                float ms = 0.0f;
+                hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+                stage_ms[k] += ms;
+            }
+        }
+    }
+    if (stage_ms)
+        for (auto& e : ev) hipEventDestroy(e);
+    return result;
+}
+
+dgfs_status dgfs_collide(const dgfs_plan* plan, const void* f, void* Q, int64_t batch, void* workspace,
+                         size_t ws_bytes, void* stream) {
+    return collide_impl(plan, f, Q, batch, workspace, ws_bytes, stream, false, nullptr);
+}
+
+dgfs_status dgfs_collide_timed(const dgfs_plan* plan, const void* f, void* Q, int64_t batch, void* workspace,
+                               size_t ws_bytes, void* stream, float* stage_ms) {
+    if (!stage_ms) return fail(DGFS_EINVAL, "stage_ms is required");
+    return collide_impl(plan, f, Q, batch, workspace, ws_bytes, stream, false, stage_ms);
+}
+
+dgfs_status dgfs_collide_pairs(const dgfs_plan* plan, const void* f, void* Q, int64_t batch, void* workspace,
+                               size_t ws_bytes, void* stream) {
+    return collide_impl(plan, f, Q, batch, workspace, ws_bytes, stream, true, nullptr);
+}
+
+dgfs_status dgfs_conserve(const dgfs_plan* plan, const void* Q_raw, double* Q_out, int64_t batch, void* stream) {
+    if (!plan) return fail(DGFS_EINVAL, "plan is NULL");
+    if (batch < 0) return fail(DGFS_EINVAL, "batch must be >= 0");
+    if (batch == 0) return DGFS_OK;
+    if (!Q_raw || !Q_out) return fail(DGFS_EINVAL, "Q_raw and Q_out are required");
+    if (plan->precision != DGFS_FP64 && static_cast<const void*>(Q_out) == Q_raw)
+        return fail(DGFS_EINVAL, "Q_out may alias Q_raw only for FP64 plans");
+    hipError_t e = dgfs::launch_conserve(*plan, Q_raw, Q_out, batch, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(DGFS_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return DGFS_OK;
+}
+
+const char* dgfs_status_string(dgfs_status status) {
+    switch (status) {
+        case DGFS_OK: return "ok";
+        case DGFS_EINVAL: return "invalid argument";
+        case DGFS_EUNSUPPORTED: return "unsupported";
+        case DGFS_ENOMEM: return "out of memory";
+        case DGFS_EDEVICE: return "device error";
+    }
+    return "unknown status";
+}
+
+const char* dgfs_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

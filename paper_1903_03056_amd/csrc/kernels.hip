@@ -1,0 +1,530 @@
+// Device kernels of the fast spectral collision operator (Sec. 4 of the paper) for
+// gfx950, and the host-side launch sequence.
+//
+// Pipeline for a slice of nb nodes (all fields complex, index space, z fastest):
+//   1. fft_pass x3     f_hat = DFT(f) / N^3                        (per node, species)
+//   2. gain_kernel     per (node, gain class, rho_q, x-chunk c):
+//                        S_q = sum_p w_p A_p B_p in physical space, where
+//                        A_p = IDFT(f_hat^i e^{+i pi rho a l.sigma_p / L})  (= f^i(v + a rho sigma_p))
+//                        B_p = IDFT(f_hat^j e^{-i pi rho b m.sigma_p / L})  (= f^j(v - b rho sigma_p)),
+//                      then the partial forward DFT of S_q over the chunk  -> P
+//   3. radial_kernel   Q_hat+ = sum_terms sum_q w_q F(|k|, rho_q) / N^3 * DFT(S_q)
+//                      L_hat  = sum_j G-_ij(|k|) f_hat^j                    -> Gt, Lt
+//   4. fft_pass x3     inverse DFT of Gt and Lt (unnormalised)
+//   5. combine         Q = Re(IDFT Gt) - f^i Re(IDFT Lt)
+//
+// The sigma-sum is taken before the forward transform of the gain because, for the
+// VHS family, F(k, rho, sigma) does not depend on sigma; with an antipodal design the
+// two orderings of an unlike pair share S_q and a like pair needs half the directions
+// (see the host set-up).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fft.hpp"
+#include "plan.hpp"
+
+namespace dgfs {
+
+// ============================================================ pencil FFT passes
+// One thread transforms one pencil of a batch of N^3 fields along AXIS (0 = x,
+// stride N^2; 1 = y, stride N; 2 = z, stride 1).  In place when in == out.
+template <typename T, int N, int AXIS, int SIGN, bool REAL_IN>
+__global__ __launch_bounds__(256) void fft_pass_kernel(const void* __restrict__ in, cx<T>* out,
+                                                       int64_t npencils, T scale) {
+    const int64_t pid = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (pid >= npencils) return;
+    constexpr int64_t N2 = int64_t(N) * N, N3 = N2 * N;
+    const int64_t field = pid / N2;
+    const int r = int(pid - field * N2);
+    int64_t base, stride;
+    if constexpr (AXIS == 0) {
+        base = field * N3 + r;
+        stride = N2;
+    } else if constexpr (AXIS == 1) {
+        base = field * N3 + int64_t(r / N) * N2 + (r % N);
+        stride = N;
+    } else {
+        base = field * N3 + int64_t(r) * N;
+        stride = 1;
+    }
+    cx<T> v[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        if constexpr (REAL_IN) {
+            v[k] = cx<T>{static_cast<const T*>(in)[base + k * stride], T(0)};
+        } else {
+            v[k] = static_cast<const cx<T>*>(in)[base + k * stride];
+        }
+    }
+    fft<N, SIGN>(v);
+#pragma unroll
+    for (int k = 0; k < N; ++k) out[base + k * stride] = scale * v[k];
+}
+
+// ================================================================ gain kernel
+template <typename T, int N, int CH, int NT>
+struct GainK {
+    static constexpr int NP = N / CH;       // x-outputs per chunk
+    static constexpr int PX = N * N / NT;   // x-pencils per thread in the first pass
+    static constexpr int ROW = N + 1;       // padded LDS row (bank spread)
+    static constexpr int LDS = NP * N * ROW;
+    static_assert(NP * CH == N, "CH must divide N");
+    static_assert(NP * N == NT, "one y/z pencil of the chunk per thread");
+    static_assert(PX * NT == N * N, "x pencils split evenly");
+};
+
+template <typename T>
+struct GainArgs {
+    const cx<T>* fhat;  // [nb][s][N^3], DFT / N^3
+    cx<T>* P;           // [nb][ncls][nrho][CH][N/CH][N][N]
+    const cx<T>* kx;    // [dirs][nrho][2][CH][N]  x-phase merged with the chunk split
+    const cx<T>* yz;    // [dirs][nrho][2][2][N]   y- and z-phases
+    const int* cls;     // [ncls][4] = i, j, ndir, dir_offset
+    const T* wdir;      // [ncls]
+    int s, ncls, nrho, nb;
+};
+
+// out[n_z] (thread (m, n_y)) = chunk c of IDFT(f_hat * phase) for one shifted field.
+// First pass along x reads the spectrum from global memory (coalesced over (l_y, l_z))
+// and keeps only the x-outputs of chunk c (decimation in frequency: the CH strided
+// input sub-sequences are combined with kxt, which carries the x-phase, the split
+// factor e^{2 pi i t c / CH} and the twiddle e^{2 pi i l' c / N}).  The y- and
+// z-phases are constant along an x-pencil and are applied to its outputs.
+template <typename T, int N, int CH, int NT>
+__device__ __forceinline__ void field_ifft(const cx<T>* __restrict__ fh, const cx<T>* __restrict__ kxt,
+                                           const cx<T>* __restrict__ yzt, cx<T>* buf, cx<T>* out) {
+    using K = GainK<T, N, CH, NT>;
+    const int tid = threadIdx.x;
+    // runtime loops here keep the x-pass loads from being hoisted en masse: the
+    // three resident pencils (A, B, S) already take most of the register file
+#pragma unroll 1
+    for (int k = 0; k < K::PX; ++k) {
+        const int P = tid + k * NT;
+        const int ly = P / N, lz = P % N;
+        const cx<T>* src = fh + P;
+        cx<T> y[K::NP];
+#pragma unroll
+        for (int l = 0; l < K::NP; ++l) y[l] = src[l * N * N] * kxt[l];
+#pragma unroll 1
+        for (int t = 1; t < CH; ++t) {
+#pragma unroll
+            for (int l = 0; l < K::NP; ++l) {
+                const int jx = l + t * K::NP;
+                cmac(y[l], src[jx * N * N], kxt[jx]);
+            }
+        }
+        fft<K::NP, +1>(y);
+        const cx<T> cyz = yzt[ly] * yzt[N + lz];
+#pragma unroll
+        for (int mm = 0; mm < K::NP; ++mm) buf[(mm * N + ly) * K::ROW + lz] = y[mm] * cyz;
+    }
+    __syncthreads();
+    const int m = tid / N, r = tid % N;
+    {
+        cx<T> v[N];
+#pragma unroll
+        for (int ly = 0; ly < N; ++ly) v[ly] = buf[(m * N + ly) * K::ROW + r];
+        fft<N, +1>(v);
+#pragma unroll
+        for (int ny = 0; ny < N; ++ny) buf[(m * N + ny) * K::ROW + r] = v[ny];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int lz = 0; lz < N; ++lz) out[lz] = buf[(m * N + r) * K::ROW + lz];
+    fft<N, +1>(out);
+    __syncthreads();
+}
+
+template <typename T, int N, int CH, int NT>
+__global__ __launch_bounds__(NT) void gain_kernel(GainArgs<T> a) {
+    using K = GainK<T, N, CH, NT>;
+    __shared__ cx<T> buf[K::LDS];
+    // Work items of one node are placed on one XCD (workgroups are dealt to the 8
+    // XCDs round-robin), so that node's spectra stay in that XCD's L2.
+    const int ipn = a.ncls * a.nrho * CH;
+    const int g = blockIdx.x;
+    const int xcd = g & 7, local = g >> 3;
+    const int b = (local / ipn) * 8 + xcd;
+    if (b >= a.nb) return;
+    int item = local % ipn;
+    const int c = item % CH;
+    item /= CH;
+    const int q = item % a.nrho;
+    const int cl = item / a.nrho;
+    const int ci = a.cls[4 * cl], cj = a.cls[4 * cl + 1];
+    const int ndir = a.cls[4 * cl + 2], doff = a.cls[4 * cl + 3];
+    const T w = a.wdir[cl];
+    constexpr int64_t N3 = int64_t(N) * N * N;
+    const cx<T>* fhi = a.fhat + (int64_t(b) * a.s + ci) * N3;
+    const cx<T>* fhj = a.fhat + (int64_t(b) * a.s + cj) * N3;
+
+    cx<T> S[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) S[n] = cx<T>{T(0), T(0)};
+
+    for (int d = 0; d < ndir; ++d) {
+        const int64_t base = (int64_t(doff + d) * a.nrho + q) * 2;
+        cx<T> A[N], B[N];
+        field_ifft<T, N, CH, NT>(fhi, a.kx + ((base + 0) * CH + c) * N, a.yz + (base + 0) * 2 * N, buf, A);
+        field_ifft<T, N, CH, NT>(fhj, a.kx + ((base + 1) * CH + c) * N, a.yz + (base + 1) * 2 * N, buf, B);
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const cx<T> ab = A[n] * B[n];
+            S[n].x = fma(w, ab.x, S[n].x);
+            S[n].y = fma(w, ab.y, S[n].y);
+        }
+    }
+
+    // forward DFT of S_q: z in registers, y through LDS, then the chunk's part of x
+    const int tid = threadIdx.x;
+    const int m = tid / N, r = tid % N;
+    fft<N, -1>(S);
+#pragma unroll
+    for (int kz = 0; kz < N; ++kz) buf[(m * N + r) * K::ROW + kz] = S[kz];
+    __syncthreads();
+    {
+        cx<T> v[N];
+#pragma unroll
+        for (int ky = 0; ky < N; ++ky) v[ky] = buf[(m * N + ky) * K::ROW + r];
+        fft<N, -1>(v);
+#pragma unroll
+        for (int ky = 0; ky < N; ++ky) buf[(m * N + ky) * K::ROW + r] = v[ky];
+    }
+    __syncthreads();
+    cx<T>* Pout = a.P + ((int64_t(b) * a.ncls + cl) * a.nrho + q) * N3 + int64_t(c) * (N3 / CH);
+#pragma unroll
+    for (int k = 0; k < K::PX; ++k) {
+        const int P = tid + k * NT;
+        const int ky = P / N, kz = P % N;
+        cx<T> v[K::NP];
+#pragma unroll
+        for (int mm = 0; mm < K::NP; ++mm) v[mm] = buf[(mm * N + ky) * K::ROW + kz];
+        fft<K::NP, -1>(v);
+#pragma unroll
+        for (int kk = 0; kk < K::NP; ++kk) Pout[kk * N * N + P] = v[kk];
+    }
+}
+
+// =============================================================== radial kernel
+template <typename T>
+struct RadialArgs {
+    const cx<T>* P;
+    const cx<T>* fhat;
+    cx<T>* Gt;          // [nb][nslots][N^3]
+    cx<T>* Lt;          // [nb][nslots][N^3]
+    const T* F;         // [nftab][nrho][K2]  w_q F(|k|, rho_q) / N^3
+    const T* G;         // [ngtab][K2]        G-(|k|)
+    const cx<T>* tw;    // [N][CH]  e^{-2 pi i kx c / N}
+    const int* slots;   // [nslots][5]
+    const int* gterms;  // [..][2]
+    const int* lterms;  // [..][2]
+    int s, ncls, nrho, nb, nslots, K2;
+};
+
+template <typename T, int N, int CH>
+__global__ __launch_bounds__(256) void radial_kernel(RadialArgs<T> a) {
+    constexpr int NP = N / CH;
+    constexpr int64_t N2 = int64_t(N) * N, N3 = N2 * N, PER = int64_t(NP) * N2;
+    const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (t >= int64_t(a.nb) * a.nslots * PER) return;
+    const int e = int(t % PER);
+    const int64_t bs = t / PER;
+    const int slot = int(bs % a.nslots);
+    const int b = int(bs / a.nslots);
+    const int kz = e % N, ky = (e / N) % N, kxp = e / (N * N);
+    auto sq = [](int k) {
+        const int mk = k < N / 2 ? k : k - N;
+        return mk * mk;
+    };
+    const int kyz2 = sq(ky) + sq(kz);
+    int k2[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) k2[j] = sq(kxp + j * NP) + kyz2;
+    const int* sd = a.slots + 5 * slot;
+    const int sp = sd[0], g0 = sd[1], ng = sd[2], l0 = sd[3], nl = sd[4];
+
+    cx<T> acc[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) acc[j] = cx<T>{T(0), T(0)};
+    for (int gi = 0; gi < ng; ++gi) {
+        const int cl = a.gterms[2 * (g0 + gi)], ft = a.gterms[2 * (g0 + gi) + 1];
+        const cx<T>* Pb = a.P + (int64_t(b) * a.ncls + cl) * a.nrho * N3 + e;
+        const T* Ft = a.F + int64_t(ft) * a.nrho * a.K2;
+        for (int q = 0; q < a.nrho; ++q) {
+            cx<T> pc[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) pc[c] = Pb[int64_t(q) * N3 + c * PER];
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int kx = kxp + j * NP;
+                cx<T> Sk = pc[0];
+#pragma unroll
+                for (int c = 1; c < CH; ++c) cmac(Sk, a.tw[kx * CH + c], pc[c]);
+                const T fq = Ft[q * a.K2 + k2[j]];
+                acc[j].x = fma(fq, Sk.x, acc[j].x);
+                acc[j].y = fma(fq, Sk.y, acc[j].y);
+            }
+        }
+    }
+    cx<T> lac[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) lac[j] = cx<T>{T(0), T(0)};
+    for (int li = 0; li < nl; ++li) {
+        const int sj = a.lterms[2 * (l0 + li)], gt = a.lterms[2 * (l0 + li) + 1];
+        const cx<T>* fj = a.fhat + (int64_t(b) * a.s + sj) * N3 + ky * N + kz;
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int kx = kxp + j * NP;
+            const T gm = a.G[int64_t(gt) * a.K2 + k2[j]];
+            const cx<T> v = fj[kx * N2];
+            lac[j].x = fma(gm, v.x, lac[j].x);
+            lac[j].y = fma(gm, v.y, lac[j].y);
+        }
+    }
+    (void)sp;
+    const int64_t ob = (int64_t(b) * a.nslots + slot) * N3 + ky * N + kz;
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+        const int kx = kxp + j * NP;
+        a.Gt[ob + kx * N2] = acc[j];
+        a.Lt[ob + kx * N2] = lac[j];
+    }
+}
+
+// ============================================================ combine kernel
+template <typename T>
+__global__ __launch_bounds__(256) void combine_kernel(const cx<T>* __restrict__ Gt, const cx<T>* __restrict__ Lt,
+                                                      const T* __restrict__ f, T* __restrict__ Q,
+                                                      const int* __restrict__ slots, int nslots, int s,
+                                                      int64_t n3, int64_t total) {
+    const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (t >= total) return;
+    const int64_t n = t % n3;
+    const int64_t bs = t / n3;
+    const int slot = int(bs % nslots);
+    const int64_t b = bs / nslots;
+    const int sp = slots[5 * slot];
+    Q[t] = Gt[t].x - f[(b * s + sp) * n3 + n] * Lt[t].x;
+}
+
+// ========================================================= FP64 conservation
+// One workgroup per node: the s+4 invariants A Q in FP64, lambda = (A A^T)^{-1} A Q,
+// then Q_out = Q - A^T lambda.  Rows of A: h^3 on species i (s rows), m_i h^3 v_d
+// (3 rows), m_i h^3 |v|^2 (1 row).
+template <typename TIN>
+__global__ __launch_bounds__(1024) void conserve_kernel(const TIN* Q, double* out, const double* __restrict__ Minv,
+                                                        const double* __restrict__ mass, int s, int N, double L) {
+    constexpr int R = 12;  // s + 4 <= 12
+    __shared__ double red[16][R];
+    __shared__ double lam[R];
+    const int b = blockIdx.x;
+    const int64_t n3 = int64_t(N) * N * N, tot = int64_t(s) * n3;
+    const TIN* q = Q + int64_t(b) * tot;
+    double* o = out + int64_t(b) * tot;
+    const double h = 2.0 * L / N, h3 = h * h * h;
+    const int nr = s + 4;
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    for (int64_t idx = threadIdx.x; idx < tot; idx += 1024) {
+        const int i = int(idx / n3);
+        const int n = int(idx - int64_t(i) * n3);
+        const double vx = -L + (n / (N * N)) * h, vy = -L + ((n / N) % N) * h, vz = -L + (n % N) * h;
+        const double val = double(q[idx]);
+        const double mh = mass[i] * h3 * val;
+#pragma unroll
+        for (int r = 0; r < R - 4; ++r)
+            if (r == i) acc[r] += h3 * val;
+        acc[R - 4] += mh * vx;
+        acc[R - 3] += mh * vy;
+        acc[R - 2] += mh * vz;
+        acc[R - 1] += mh * (vx * vx + vy * vy + vz * vz);
+    }
+    // block reduction
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        double v = acc[r];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        acc[r] = v;
+    }
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (lane == 0)
+        for (int r = 0; r < R; ++r) red[wave][r] = acc[r];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot_r[R];
+        for (int r = 0; r < R; ++r) {
+            double v = 0.0;
+            for (int w = 0; w < int(blockDim.x / 64); ++w) v += red[w][r];
+            tot_r[r] = v;
+        }
+        // invariant vector in the order (species 0..s-1, px, py, pz, energy)
+        double aq[R];
+        for (int i = 0; i < s; ++i) aq[i] = tot_r[i];
+        for (int d = 0; d < 4; ++d) aq[s + d] = tot_r[R - 4 + d];
+        for (int r = 0; r < nr; ++r) {
+            double v = 0.0;
+            for (int c = 0; c < nr; ++c) v += Minv[r * nr + c] * aq[c];
+            lam[r] = v;
+        }
+    }
+    __syncthreads();
+    for (int64_t idx = threadIdx.x; idx < tot; idx += 1024) {
+        const int i = int(idx / n3);
+        const int n = int(idx - int64_t(i) * n3);
+        const double vx = -L + (n / (N * N)) * h, vy = -L + ((n / N) % N) * h, vz = -L + (n % N) * h;
+        const double mh = mass[i] * h3;
+        const double corr = lam[i] * h3 + mh * (lam[s] * vx + lam[s + 1] * vy + lam[s + 2] * vz +
+                                                lam[s + 3] * (vx * vx + vy * vy + vz * vz));
+        o[idx] = double(q[idx]) - corr;
+    }
+}
+
+// ================================================================== launches
+namespace {
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+template <typename T, int N>
+hipError_t fft3d(cx<T>* data, const void* real_in, int64_t nfields, int sign, T scale, hipStream_t st) {
+    const int64_t np = nfields * N * N;
+    const dim3 grid(unsigned((np + 255) / 256)), block(256);
+    if (sign < 0) {
+        // forward from real input: z (real -> complex), y, x (with scale)
+        fft_pass_kernel<T, N, 2, -1, true><<<grid, block, 0, st>>>(real_in, data, np, T(1));
+        fft_pass_kernel<T, N, 1, -1, false><<<grid, block, 0, st>>>(data, data, np, T(1));
+        fft_pass_kernel<T, N, 0, -1, false><<<grid, block, 0, st>>>(data, data, np, scale);
+    } else {
+        fft_pass_kernel<T, N, 0, +1, false><<<grid, block, 0, st>>>(data, data, np, T(1));
+        fft_pass_kernel<T, N, 1, +1, false><<<grid, block, 0, st>>>(data, data, np, T(1));
+        fft_pass_kernel<T, N, 2, +1, false><<<grid, block, 0, st>>>(data, data, np, scale);
+    }
+    return hipGetLastError();
+}
+
+// ev (optional): 6 events recorded at the stage boundaries (start, after forward FFT,
+// after gain, after radial, after inverse FFTs, after combine).
+template <typename T, int N, int CH, int NT>
+hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, bool pairs, hipStream_t st,
+                     hipEvent_t* ev) {
+    auto mark = [&](int k) {
+        if (ev) hipEventRecord(ev[k], st);
+    };
+    const SlotSet& ss = pairs ? p.pair_slots : p.sum_slots;
+    constexpr int64_t N3 = int64_t(N) * N * N;
+    const int ncls = int(p.classes.size());
+    char* w = static_cast<char*>(ws);
+    cx<T>* fhat = reinterpret_cast<cx<T>*>(w);
+    w += align256(sizeof(cx<T>) * nb * p.s * N3);
+    cx<T>* P = reinterpret_cast<cx<T>*>(w);
+    w += align256(sizeof(cx<T>) * int64_t(nb) * ncls * p.nrho * N3);
+    cx<T>* Gt = reinterpret_cast<cx<T>*>(w);
+    cx<T>* Lt = Gt + int64_t(nb) * ss.nslots * N3;  // contiguous with Gt
+
+    const char* dev = static_cast<const char*>(p.dev);
+    mark(0);
+    hipError_t e = fft3d<T, N>(fhat, f, int64_t(nb) * p.s, -1, T(1.0 / double(N3)), st);
+    if (e != hipSuccess) return e;
+    mark(1);
+
+    GainArgs<T> ga;
+    ga.fhat = fhat;
+    ga.P = P;
+    ga.kx = reinterpret_cast<const cx<T>*>(dev + p.off_kx);
+    ga.yz = reinterpret_cast<const cx<T>*>(dev + p.off_yz);
+    ga.cls = reinterpret_cast<const int*>(dev + p.off_cls);
+    ga.wdir = reinterpret_cast<const T*>(dev + p.off_wdir);
+    ga.s = p.s;
+    ga.ncls = ncls;
+    ga.nrho = p.nrho;
+    ga.nb = nb;
+    const int64_t ipn = int64_t(ncls) * p.nrho * CH;
+    const int64_t groups = ((nb + 7) / 8) * 8 * ipn;
+    gain_kernel<T, N, CH, NT><<<dim3(unsigned(groups)), dim3(NT), 0, st>>>(ga);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    mark(2);
+
+    RadialArgs<T> ra;
+    ra.P = P;
+    ra.fhat = fhat;
+    ra.Gt = Gt;
+    ra.Lt = Lt;
+    ra.F = reinterpret_cast<const T*>(dev + p.off_F);
+    ra.G = reinterpret_cast<const T*>(dev + p.off_G);
+    ra.tw = reinterpret_cast<const cx<T>*>(dev + p.off_tw);
+    ra.slots = reinterpret_cast<const int*>(dev + ss.off_slots);
+    ra.gterms = reinterpret_cast<const int*>(dev + ss.off_gterms);
+    ra.lterms = reinterpret_cast<const int*>(dev + ss.off_lterms);
+    ra.s = p.s;
+    ra.ncls = ncls;
+    ra.nrho = p.nrho;
+    ra.nb = nb;
+    ra.nslots = ss.nslots;
+    ra.K2 = p.K2;
+    const int64_t rthreads = int64_t(nb) * ss.nslots * (N3 / CH);
+    radial_kernel<T, N, CH><<<dim3(unsigned((rthreads + 255) / 256)), dim3(256), 0, st>>>(ra);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    mark(3);
+
+    e = fft3d<T, N>(Gt, nullptr, 2 * int64_t(nb) * ss.nslots, +1, T(1), st);
+    if (e != hipSuccess) return e;
+    mark(4);
+
+    const int64_t total = int64_t(nb) * ss.nslots * N3;
+    combine_kernel<T><<<dim3(unsigned((total + 255) / 256)), dim3(256), 0, st>>>(
+        Gt, Lt, f, Q, ra.slots, ss.nslots, p.s, N3, total);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    mark(5);
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t dispatch(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, bool pairs, hipStream_t st,
+                    hipEvent_t* ev) {
+    switch (p.N) {
+        case 16: return run_slice<T, 16, 1, 256>(p, f, Q, nb, ws, pairs, st, ev);
+        case 24: return run_slice<T, 24, 3, 192>(p, f, Q, nb, ws, pairs, st, ev);
+        case 32:
+            if constexpr (sizeof(T) == 4) return run_slice<T, 32, 4, 256>(p, f, Q, nb, ws, pairs, st, ev);
+            else return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+bool gain_geometry(int N, int precision, GainGeometry* g) {
+    switch (N) {
+        case 16: *g = {1, 256}; return true;
+        case 24: *g = {3, 192}; return true;
+        case 32:
+            if (precision != DGFS_FP32) return false;
+            *g = {4, 256};
+            return true;
+        default: return false;
+    }
+}
+
+hipError_t launch_collide(const dgfs_plan& p, const void* f, void* Q, int64_t nb, void* ws, bool pairs,
+                          hipStream_t st, hipEvent_t* ev) {
+    if (p.precision == DGFS_FP64)
+        return dispatch<double>(p, static_cast<const double*>(f), static_cast<double*>(Q), int(nb), ws, pairs, st,
+                                ev);
+    return dispatch<float>(p, static_cast<const float*>(f), static_cast<float*>(Q), int(nb), ws, pairs, st, ev);
+}
+
+hipError_t launch_conserve(const dgfs_plan& p, const void* Q, double* out, int64_t nb, hipStream_t st) {
+    const char* dev = static_cast<const char*>(p.dev);
+    const double* minv = reinterpret_cast<const double*>(dev + p.off_minv);
+    const double* mass = minv + (p.s + 4) * (p.s + 4);
+    if (p.precision == DGFS_FP64)
+        conserve_kernel<double><<<dim3(unsigned(nb)), dim3(1024), 0, st>>>(static_cast<const double*>(Q), out, minv,
+                                                                          mass, p.s, p.N, p.L);
+    else
+        conserve_kernel<float><<<dim3(unsigned(nb)), dim3(1024), 0, st>>>(static_cast<const float*>(Q), out, minv,
+                                                                         mass, p.s, p.N, p.L);
+    return hipGetLastError();
+}
+
+}  // namespace dgfs

@@ -1,0 +1,87 @@
+// Internal plan object of the collision library and the device launch interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dgfs.h"
+
+namespace dgfs {
+
+// Launch geometry of the fused gain kernel for one velocity resolution N:
+// CH   chunks of the output grid along x (each work item owns x-indices = c mod CH),
+// NT   threads per work item (one y/z pencil of the chunk per thread).
+struct GainGeometry {
+    int CH;
+    int NT;
+};
+
+bool gain_geometry(int N, int precision, GainGeometry* g);
+
+// One "gain class": the S_q field sum_p w A_p B_p with A = f^i shifted by +a rho sigma_p,
+// B = f^j shifted by -b rho sigma_p.  With an antipodal design one class serves both
+// orderings of an unlike pair, and a like pair needs only half of the directions.
+struct GainClass {
+    int i, j;
+    double a, b;
+    int ndir;        // directions of this class
+    int dir_offset;  // first global direction index in the phase tables
+    double weight;   // sphere weight per direction (4 pi / M, doubled for a halved like pair)
+};
+
+struct PairParams {
+    double a, b, gamma, C, R;
+    std::vector<double> rho, wrho;
+};
+
+// Device-side integer descriptors (all int32):
+//   class:  i, j, ndir, dir_offset
+//   slot:   species, gain_begin, gain_count, loss_begin, loss_count
+//   gain term: class, F table
+//   loss term: species j, G table
+struct SlotSet {
+    int nslots = 0;
+    std::vector<int> slots, gterms, lterms;
+    size_t off_slots = 0, off_gterms = 0, off_lterms = 0;  // byte offsets in the device block
+};
+
+}  // namespace dgfs
+
+struct dgfs_plan {
+    int s = 0, N = 0, M = 0, nrho = 0, precision = 0;
+    double L = 0;
+    std::vector<double> mass;
+    dgfs::GainGeometry geo{};
+    std::vector<double> sigma;  // design, [M][3]
+    bool antipodal = false;
+    std::vector<dgfs::PairParams> pair;  // [s*s]
+    std::vector<dgfs::GainClass> classes;
+    int total_dirs = 0;
+    int nftab = 0, ngtab = 0, K2 = 0;
+    dgfs::SlotSet sum_slots, pair_slots;
+
+    int device = 0;
+    void* dev = nullptr;  // one block holding every table
+    size_t dev_bytes = 0;
+    // byte offsets of the tables in `dev`
+    size_t off_kx = 0, off_yz = 0, off_F = 0, off_G = 0, off_tw = 0, off_cls = 0, off_wdir = 0;
+    size_t off_minv = 0;  // (s+4)^2 doubles, inverse Gram matrix of the invariants
+
+    size_t elem() const { return precision == DGFS_FP64 ? sizeof(double) : sizeof(float); }
+    size_t n3() const { return size_t(N) * N * N; }
+    // workspace bytes per node
+    size_t ws_per_node(bool pairs) const;
+};
+
+namespace dgfs {
+// Launch the full collide pipeline for nb nodes on `stream`.
+// ev: NULL, or 6 events recorded at the stage boundaries of the slice.
+hipError_t launch_collide(const dgfs_plan& p, const void* f, void* Q, int64_t nb, void* ws,
+                          bool pairs, hipStream_t stream, hipEvent_t* ev);
+hipError_t launch_conserve(const dgfs_plan& p, const void* Q, double* out, int64_t nb,
+                           hipStream_t stream);
+}  // namespace dgfs

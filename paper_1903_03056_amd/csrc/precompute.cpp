@@ -1,0 +1,206 @@
+#include "precompute.hpp"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+
+namespace dgfs {
+namespace pre {
+
+namespace {
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// Legendre P_n(x) and P_n'(x) by the three-term recurrence.
+void legendre(int n, double x, double& p, double& dp) {
+    double p0 = 1.0, p1 = x;
+    if (n == 0) {
+        p = 1.0;
+        dp = 0.0;
+        return;
+    }
+    for (int k = 2; k <= n; ++k) {
+        double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+    }
+    p = p1;
+    dp = n * (x * p1 - p0) / (x * x - 1.0);
+}
+}  // namespace
+
+void gauss_legendre(int n, double R, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double t = std::cos(kPi * (i + 0.75) / (n + 0.5));
+        double p = 0, dp = 0;
+        for (int it = 0; it < 100; ++it) {
+            legendre(n, t, p, dp);
+            double dt = p / dp;
+            t -= dt;
+            if (std::fabs(dt) < 1e-17) break;
+        }
+        legendre(n, t, p, dp);
+        // node t in (-1, 1), descending in i; map to [0, R] ascending
+        x[n - 1 - i] = 0.5 * R * (t + 1.0);
+        w[n - 1 - i] = 0.5 * R * 2.0 / ((1.0 - t * t) * dp * dp);
+    }
+}
+
+namespace {
+void lexsort(std::vector<double>& pts) {
+    const int M = int(pts.size() / 3);
+    std::vector<std::array<double, 3>> v(M);
+    for (int i = 0; i < M; ++i) v[i] = {pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]};
+    std::sort(v.begin(), v.end());
+    for (int i = 0; i < M; ++i)
+        for (int d = 0; d < 3; ++d) pts[3 * i + d] = v[i][d];
+}
+
+// Roots of 105 t^3 - 105 t^2 + 21 t - 1 in (0, 1), ascending, by bracketing + bisection.
+std::array<double, 3> cubic_roots() {
+    auto p = [](double t) { return ((105.0 * t - 105.0) * t + 21.0) * t - 1.0; };
+    std::array<double, 3> r{};
+    int found = 0;
+    const int steps = 1000;
+    for (int k = 0; k < steps && found < 3; ++k) {
+        double a = double(k) / steps, b = double(k + 1) / steps;
+        if ((p(a) < 0) != (p(b) < 0)) {
+            for (int it = 0; it < 200; ++it) {
+                double m = 0.5 * (a + b);
+                if ((p(a) < 0) != (p(m) < 0)) b = m; else a = m;
+            }
+            r[found++] = 0.5 * (a + b);
+        }
+    }
+    return r;
+}
+}  // namespace
+
+bool design(int M, std::vector<double>& pts) {
+    pts.clear();
+    if (M == 6) {
+        for (int s : {1, -1})
+            for (int d = 0; d < 3; ++d) {
+                double p[3] = {0, 0, 0};
+                p[d] = s;
+                pts.insert(pts.end(), p, p + 3);
+            }
+    } else if (M == 12) {
+        const double phi = 0.5 * (1.0 + std::sqrt(5.0));
+        const double nrm = std::sqrt(1.0 + phi * phi);
+        for (int s1 : {1, -1})
+            for (int s2 : {1, -1}) {
+                double x = 0.0, y = s1, z = s2 * phi;
+                double cyc[3][3] = {{x, y, z}, {z, x, y}, {y, z, x}};
+                for (auto& c : cyc)
+                    for (double v : c) pts.push_back(v / nrm);
+            }
+    } else if (M == 24) {
+        // Orbit of g under the 24 cube rotations (signed permutations, det +1); a
+        // 7-design because the invariant harmonics of degree 4 and 6 vanish at g.
+        std::array<double, 3> t = cubic_roots();
+        double g[3] = {std::sqrt(t[0]), std::sqrt(t[1]), std::sqrt(t[2])};
+        int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+        int parity[6] = {1, -1, -1, 1, 1, -1};
+        for (int pi = 0; pi < 6; ++pi)
+            for (int sgn = 0; sgn < 8; ++sgn) {
+                int s[3] = {(sgn & 1) ? -1 : 1, (sgn & 2) ? -1 : 1, (sgn & 4) ? -1 : 1};
+                if (parity[pi] * s[0] * s[1] * s[2] != 1) continue;
+                for (int r = 0; r < 3; ++r) pts.push_back(s[r] * g[perm[pi][r]]);
+            }
+    } else {
+        return false;
+    }
+    lexsort(pts);
+    return true;
+}
+
+bool antipodal(const std::vector<double>& pts) {
+    const int M = int(pts.size() / 3);
+    for (int i = 0; i < M; ++i) {
+        bool hit = false;
+        for (int j = 0; j < M && !hit; ++j) {
+            double d = 0;
+            for (int k = 0; k < 3; ++k) d += std::fabs(pts[3 * i + k] + pts[3 * j + k]);
+            hit = d < 1e-12;
+        }
+        if (!hit) return false;
+    }
+    return true;
+}
+
+double support_radius(double L, double mi, double mj) {
+    return 2.0 * L / (std::max(4.0 * mj / (mi + mj), 2.0) + std::sqrt(1.0 + mj / mi) + 1.0);
+}
+
+double truncation_radius(double L, double mi, double mj) {
+    return 2.0 * std::min(support_radius(L, mi, mj), support_radius(L, mj, mi));
+}
+
+double sinc(double x) {
+    if (std::fabs(x) < 1e-4) {
+        double x2 = x * x;
+        return 1.0 - x2 / 6.0 + x2 * x2 / 120.0;
+    }
+    return std::sin(x) / x;
+}
+
+double kernel_mode(double kabs, double rho, double a, double gamma, double C, double L) {
+    return 4.0 * kPi * C * std::pow(rho, gamma + 2.0) * sinc(kPi * a * rho * kabs / L);
+}
+
+namespace {
+// 20-point Gauss-Legendre on [-1, 1], built once.
+struct GL20 {
+    std::vector<double> x, w;
+    GL20() {
+        gauss_legendre(20, 2.0, x, w);
+        for (auto& v : x) v -= 1.0;
+    }
+};
+const GL20& gl20() {
+    static GL20 g;
+    return g;
+}
+
+double composite(double R, double gamma, double kappa, int refine) {
+    const GL20& g = gl20();
+    auto f = [&](double r) { return std::pow(r, gamma + 2.0) * sinc(kappa * r); };
+    // graded breakpoints R 2^-k, k = 0..40, each dyadic interval [u, 2u] split into
+    // pieces no wider than ~ (1/refine) of the local oscillation length.
+    double total = 0.0;
+    double hi = R;
+    for (int k = 0; k < 40; ++k) {
+        double lo = hi * 0.5;
+        double width = hi - lo;
+        double osc = 6.0 / (1.0 + kappa);  // about one period of sinc per piece
+        int pieces = std::max(1, int(std::ceil(width / osc))) * refine;
+        double h = width / pieces;
+        for (int p = 0; p < pieces; ++p) {
+            double a = lo + p * h, c = 0.5 * h, mid = a + c;
+            double s = 0.0;
+            for (size_t q = 0; q < g.x.size(); ++q) s += g.w[q] * f(mid + c * g.x[q]);
+            total += c * s;
+        }
+        hi = lo;
+    }
+    return total;  // the remaining [0, R 2^-40] contributes < R^{gamma+3} 2^-120
+}
+}  // namespace
+
+double loss_weight(double mabs, double R, double gamma, double C, double L) {
+    const double kappa = kPi * mabs / L;
+    const double scale = std::pow(R, gamma + 3.0) / (gamma + 3.0);
+    double prev = composite(R, gamma, kappa, 1);
+    double cur = prev;
+    for (int refine = 2; refine <= 64; refine *= 2) {
+        cur = composite(R, gamma, kappa, refine);
+        if (std::fabs(cur - prev) <= 1e-15 * scale) break;
+        prev = cur;
+    }
+    return 16.0 * kPi * kPi * C * cur;
+}
+
+}  // namespace pre
+}  // namespace dgfs

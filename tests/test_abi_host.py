@@ -1,0 +1,107 @@
+"""Host-side checks of the C ABI: the library loads, exports what include/dgfs.h
+declares, validates problems, and its FP64 precomputation agrees with the oracle.
+No GPU is used."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import params as OP, quadrature as OQ, spectral as OS
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1903_03056_amd", "libdgfs.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libdgfs.so not built")
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "dgfs.h")).read()
+    return sorted(set(re.findall(r"\b(dgfs_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(LIB)
+    names = _declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_names_match_header():
+    from paper_1903_03056_amd import _lib
+    assert sorted(_lib.EXPORTED) == _declared_functions()
+
+
+def _kern(masses, omega):
+    from paper_1903_03056_amd import vhs_kernel
+    return vhs_kernel(masses, omega)
+
+
+def test_check_problem_accepts_and_rejects():
+    from paper_1903_03056_amd import check_problem
+    from paper_1903_03056_amd._lib import DGFS_EINVAL, DGFS_EUNSUPPORTED, DGFS_OK
+    m = (1.0, 2.0)
+    k = _kern(m, 0.74)
+    assert check_problem(m, 6.0, 32, 12, 16, k) == DGFS_OK
+    assert check_problem(m, 5.0, 16, 6, 8, _kern(m, 1.0), "f64") == DGFS_OK
+    assert check_problem(m, 6.0, 32, 7, 16, k) == DGFS_EINVAL           # no design
+    assert check_problem(m, -1.0, 32, 12, 16, k) == DGFS_EINVAL         # L
+    assert check_problem(m, 6.0, 31, 12, 16, k) == DGFS_EINVAL          # odd N
+    assert check_problem(m, 6.0, 32, 12, 0, k) == DGFS_EINVAL           # n_rho
+    assert check_problem((1.0, -2.0), 6.0, 32, 12, 16, k) == DGFS_EINVAL
+    bad = [list(r) for r in k]
+    bad[0][1] = (0.74, 1.0, k[0][1][2] * 1.01)                           # asymmetric C
+    assert check_problem(m, 6.0, 32, 12, 16, bad) == DGFS_EINVAL
+    bad = [list(r) for r in k]
+    bad[0][0] = (0.3, 1.0, 1.0)                                          # omega out of range
+    assert check_problem(m, 6.0, 32, 12, 16, bad) == DGFS_EINVAL
+    vss = [[(0.74, 1.4, 1.0)] * 2 for _ in range(2)]
+    assert check_problem(m, 6.0, 32, 12, 16, vss) == DGFS_EUNSUPPORTED   # VSS not implemented
+    assert check_problem(m, 6.0, 20, 12, 16, k) == DGFS_EUNSUPPORTED     # no kernels for N=20
+    assert check_problem(m, 6.0, 32, 12, 16, k, "f64") == DGFS_EUNSUPPORTED
+    assert check_problem(m, 6.0, 32, 12, 16, k, L_species=(6.0, 1.0)) == DGFS_EUNSUPPORTED
+
+
+def test_plan_create_without_device_reports_error():
+    """Creating a plan needs a device; on a machine without one the call fails cleanly."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    from paper_1903_03056_amd import CollisionPlan
+    from paper_1903_03056_amd._lib import DgfsError
+    with pytest.raises(DgfsError):
+        CollisionPlan((1.0, 2.0), 16, 5.0, 6, 8, omega=1.0, precision="f64")
+
+
+@pytest.mark.parametrize("M", [6, 12, 24])
+def test_design_matches_oracle(M):
+    from paper_1903_03056_amd import design
+    assert np.allclose(design(M), OQ.spherical_design(M), atol=1e-15)
+
+
+@pytest.mark.parametrize("masses,omega,L,N,nrho", [((1.0, 2.0), 0.74, 6.0, 32, 16),
+                                                   ((1.0, 2.0), 1.0, 5.0, 16, 8),
+                                                   ((1.0, 4.0, 20.0), 0.5, 6.0, 24, 12)])
+def test_host_tables_match_oracle(masses, omega, L, N, nrho):
+    """R_ij, Gauss-Legendre nodes/weights, C_ij and the loss weight G-(|m|) computed by
+    the library's own FP64 host code agree with the oracle's independent routines."""
+    from paper_1903_03056_amd import pair_tables
+    k = _kern(masses, omega)
+    s = len(masses)
+    for i in range(s):
+        for j in range(s):
+            t = pair_tables(masses, L, N, 12, nrho, k, i, j)
+            pr = OS.make_pair(masses[i], masses[j], omega, OP.vss_prefactor(masses[i], masses[j], omega), L, nrho,
+                              *OQ.design_quadrature(12))
+            assert t["a"] == pytest.approx(pr.a, rel=1e-15) and t["b"] == pytest.approx(pr.b, rel=1e-15)
+            assert t["R"] == pytest.approx(pr.R, rel=1e-15)
+            assert t["C"] == pytest.approx(pr.C, rel=1e-14)
+            assert np.allclose(t["rho"], pr.rho, rtol=1e-14, atol=0)
+            assert np.allclose(t["wrho"], pr.wrho, rtol=1e-13, atol=0)
+            k2 = np.arange(3 * (N // 2) ** 2 + 1)
+            ref = OS.loss_weight(np.sqrt(k2), pr.R, pr.gamma, pr.C, L)
+            scale = np.abs(ref).max()
+            assert np.abs(t["loss_by_k2"] - ref).max() <= 1e-13 * scale
+            assert t["ndir"] == (6 if i == j else 12)
