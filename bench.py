@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one plain device copy of 2 x 256 MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -119,6 +121,14 @@ def main():
     Qc = torch.empty(f.shape, dtype=torch.float64, device=dev)
     st = torch.cuda.current_stream(dev)
 
+    if args.copy_probe:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {src.numel() * 4} bytes read + {dst.numel() * 4} bytes written")
+        del src, dst
     for _ in range(args.warmup):
         plan.collide(f, out=Q, workspace=ws)
         plan.conserve(Q, out=Qc)
