@@ -9,7 +9,8 @@ import ctypes
 import os
 from ctypes import POINTER, c_double, c_int32, c_int64, c_size_t, c_void_p
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdgfs.so")
+LIB_PATH = os.environ.get("DGFS_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                          "libdgfs.so")
 
 DGFS_OK, DGFS_EINVAL, DGFS_EUNSUPPORTED, DGFS_ENOMEM, DGFS_EDEVICE = 0, -1, -2, -3, -4
 DGFS_FP32, DGFS_FP64 = 0, 1

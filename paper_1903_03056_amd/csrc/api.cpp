@@ -143,6 +143,7 @@ void build_tables(dgfs_plan& P, std::vector<char>& blob) {
     // ---------------- phase tables [dirs][nrho][2][CH][N] and [dirs][nrho][2][2][N]
     std::vector<std::complex<double>> kx(size_t(P.total_dirs) * nrho * 2 * CH * N);
     std::vector<std::complex<double>> yz(size_t(P.total_dirs) * nrho * 2 * 2 * N);
+    std::vector<double> nyq(size_t(P.total_dirs) * nrho * 2);
     std::vector<int> cls;
     std::vector<double> wdir;
     std::vector<int> design_index;  // global direction -> design point
@@ -187,6 +188,7 @@ void build_tables(dgfs_plan& P, std::vector<char>& blob) {
                                                    2.0 * kPi * (double(t * cc) / CH + double(l * cc) / N);
                                 kx[(base * CH + cc) * N + jx] = std::polar(1.0, ang);
                             }
+                    nyq[base] = 2.0 * std::sin(th[0] * (N / 2));
                     for (int jj = 0; jj < N; ++jj) {
                         yz[(base * 2 + 0) * N + jj] = std::polar(1.0, th[1] * signed_mode(jj, N));
                         yz[(base * 2 + 1) * N + jj] = std::polar(1.0, th[2] * signed_mode(jj, N));
@@ -197,6 +199,7 @@ void build_tables(dgfs_plan& P, std::vector<char>& blob) {
     }
     push_cplx<T>(blob, P.off_kx, kx);
     push_cplx<T>(blob, P.off_yz, yz);
+    push_real<T>(blob, P.off_nyq, nyq);
     push_int(blob, P.off_cls, cls);
     push_real<T>(blob, P.off_wdir, wdir);
 

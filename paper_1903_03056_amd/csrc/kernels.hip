@@ -63,15 +63,22 @@ __global__ __launch_bounds__(256) void fft_pass_kernel(const void* __restrict__ 
 }
 
 // ================================================================ gain kernel
-template <typename T, int N, int CH, int NT>
+// Geometry of one work item: the x-chunk c (x-indices = c mod CH, NP = N/CH of them)
+// of one S_q field.  Each y/z pencil of the chunk is shared by CZ thread groups: group
+// cz keeps the outputs with index = cz mod CZ (decimation in frequency), so a thread
+// holds NS = N/CZ values per field.  The group index is uniform per wavefront
+// (NTC = NP*N is a multiple of 64), so every twiddle is a compile-time constant.
+template <typename T, int N, int CH, int CZ>
 struct GainK {
-    static constexpr int NP = N / CH;       // x-outputs per chunk
-    static constexpr int PX = N * N / NT;   // x-pencils per thread in the first pass
-    static constexpr int ROW = N + 1;       // padded LDS row (bank spread)
+    static constexpr int NP = N / CH;
+    static constexpr int NS = N / CZ;
+    static constexpr int NTC = NP * N;
+    static constexpr int NT = NTC * CZ;
+    static constexpr int PX = (N * N + NT - 1) / NT;   // x-pencils per thread (guarded)
+    static constexpr int ROW = N + 1;                  // padded LDS row (bank spread)
     static constexpr int LDS = NP * N * ROW;
-    static_assert(NP * CH == N, "CH must divide N");
-    static_assert(NP * N == NT, "one y/z pencil of the chunk per thread");
-    static_assert(PX * NT == N * N, "x pencils split evenly");
+    static_assert(NP * CH == N && NS * CZ == N, "CH and CZ must divide N");
+    static_assert(NTC % 64 == 0, "a CZ group must be whole wavefronts");
 };
 
 template <typename T>
@@ -80,28 +87,116 @@ struct GainArgs {
     cx<T>* P;           // [nb][ncls][nrho][CH][N/CH][N][N]
     const cx<T>* kx;    // [dirs][nrho][2][CH][N]  x-phase merged with the chunk split
     const cx<T>* yz;    // [dirs][nrho][2][2][N]   y- and z-phases
+    const T* nyq;       // [dirs][nrho][2]         2 sin(theta_x N / 2) of the x-phase
     const int* cls;     // [ncls][4] = i, j, ndir, dir_offset
     const T* wdir;      // [ncls]
     int s, ncls, nrho, nb;
 };
 
-// out[n_z] (thread (m, n_y)) = chunk c of IDFT(f_hat * phase) for one shifted field.
-// First pass along x reads the spectrum from global memory (coalesced over (l_y, l_z))
-// and keeps only the x-outputs of chunk c (decimation in frequency: the CH strided
-// input sub-sequences are combined with kxt, which carries the x-phase, the split
-// factor e^{2 pi i t c / CH} and the twiddle e^{2 pi i l' c / N}).  The y- and
-// z-phases are constant along an x-pencil and are applied to its outputs.
-template <typename T, int N, int CH, int NT>
+// out[j] = X[CZ j + CZI] of the length-N DFT (sign SIGN) of the sequence
+// x[n] = src[n * stride]: the CZ strided input sub-sequences are combined with the
+// split factors e^{SIGN 2 pi i t CZI / CZ}, twiddled by e^{SIGN 2 pi i l CZI / N},
+// then transformed with an N/CZ-point FFT.
+template <int N, int CZ, int CZI, int SIGN, int STRIDE, typename T>
+__device__ __forceinline__ void split_fft(const cx<T>* src, cx<T>* out) {
+    constexpr int NS = N / CZ;
+    static_for<0, NS>([&](auto l) {
+        cx<T> acc = src[l * STRIDE];
+        static_for<1, CZ>([&](auto t) {
+            constexpr long k = long(decltype(t)::value) * CZI;
+            acc = acc + rot<SIGN, k, CZ>(src[(l + t * NS) * STRIDE]);
+        });
+        out[l] = rot<SIGN, long(decltype(l)::value) * CZI, long(N)>(acc);
+        // keep at most a few loads in flight: the pencil's inputs are combined as they
+        // arrive instead of all being held in registers at once
+        if constexpr (decltype(l)::value % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+    });
+    fft<NS, SIGN>(out);
+}
+
+// Call f(integral_constant<int, cz>) for the runtime (wave-uniform) group index cz.
+template <int CZ, typename F>
+__device__ __forceinline__ void with_group(int cz, F&& f) {
+    if constexpr (CZ == 1) {
+        f(std::integral_constant<int, 0>{});
+    } else {
+        static_for<0, CZ>([&](auto g) {
+            if (cz == decltype(g)::value) f(g);
+        });
+    }
+}
+
+// y-pass (through LDS, in place on columns) and z-pass (rows, result kept) of one
+// field whose x-pass output is in buf; out[j] = value at z-index CZ j + cz of the
+// thread's pencil (m, r).
+template <typename T, int N, int CH, int CZ, int SIGN>
+__device__ __forceinline__ void yz_passes(cx<T>* buf, int cz, int m, int r, cx<T>* out) {
+    using K = GainK<T, N, CH, CZ>;
+    cx<T> v[K::NS];
+    with_group<CZ>(cz, [&](auto g) {
+        split_fft<N, CZ, decltype(g)::value, SIGN, K::ROW>(buf + (m * N) * K::ROW + r, v);
+    });
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < K::NS; ++j) buf[(m * N + CZ * j + cz) * K::ROW + r] = v[j];
+    __syncthreads();
+    with_group<CZ>(cz, [&](auto g) {
+        split_fft<N, CZ, decltype(g)::value, SIGN, 1>(buf + (m * N + r) * K::ROW, out);
+    });
+}
+
+// Representative x-pencils of the Hermitian pairing P = (l_y, l_z) <-> -P (mod N):
+// rows 1..N/2-1 (all l_z), then rows 0 and N/2 with l_z in 1..N/2-1, then the four
+// self-paired pencils (l_y, l_z in {0, N/2}).  Returns false for self-paired pencils.
+template <int N>
+__device__ __forceinline__ bool pencil_slot(int slot, int& ly, int& lz) {
+    constexpr int H = N / 2;
+    constexpr int RA = (H - 1) * N;
+    if (slot < RA) {
+        ly = 1 + slot / N;
+        lz = slot % N;
+        return true;
+    }
+    const int t = slot - RA;
+    if (t < 2 * (H - 1)) {
+        ly = t < H - 1 ? 0 : H;
+        lz = 1 + t % (H - 1);
+        return true;
+    }
+    const int u = t - 2 * (H - 1);
+    ly = (u >> 1) * H;
+    lz = (u & 1) * H;
+    return false;
+}
+
+// Chunk c of IDFT(f_hat * phase) for one shifted field: out[j] at (x = CH m + c,
+// y = r, z = CZ j + cz).  The x-pass reads the spectrum from global memory (coalesced
+// over (l_y, l_z)) and keeps only the chunk's x-outputs: the CH strided input
+// sub-sequences are combined with kxt, which carries the x-phase, the split factor
+// e^{2 pi i t c / CH} and the twiddle e^{2 pi i l c / N}.  The y- and z-phases are
+// constant along an x-pencil and multiply its outputs.
+//
+// f is real, so f_hat(l_x, -P) = conj(f_hat(-l_x, P)); with the linear x-phase this
+// gives, for every output x-index n, G(-P)[n] = conj(G(P)[n] + delta_P (-1)^n) where
+// delta_P = f_hat(N/2, P) (e^{i theta N/2} - e^{-i theta N/2}) accounts for the DFT
+// index N/2 standing for the mode -N/2 on both sides.  So only one pencil of each pair
+// is transformed; its partner costs a conjugate, one correction and its own y/z phase.
+template <typename T, int N, int CH, int CZ>
 __device__ __forceinline__ void field_ifft(const cx<T>* __restrict__ fh, const cx<T>* __restrict__ kxt,
-                                           const cx<T>* __restrict__ yzt, cx<T>* buf, cx<T>* out) {
-    using K = GainK<T, N, CH, NT>;
+                                           const cx<T>* __restrict__ yzt, T nyq, int c, cx<T>* buf, int cz,
+                                           int m, int r, cx<T>* out) {
+    using K = GainK<T, N, CH, CZ>;
+    constexpr int SLOTS = N * N / 2 + 2;
+    constexpr int ROUNDS = (SLOTS + K::NT - 1) / K::NT;
     const int tid = threadIdx.x;
-    // runtime loops here keep the x-pass loads from being hoisted en masse: the
-    // three resident pencils (A, B, S) already take most of the register file
+    // runtime loops keep the x-pass loads from being hoisted en masse
 #pragma unroll 1
-    for (int k = 0; k < K::PX; ++k) {
-        const int P = tid + k * NT;
-        const int ly = P / N, lz = P % N;
+    for (int k = 0; k < ROUNDS; ++k) {
+        const int slot = tid + k * K::NT;
+        if (ROUNDS * K::NT != SLOTS && slot >= SLOTS) break;
+        int ly, lz;
+        const bool paired = pencil_slot<N>(slot, ly, lz);
+        const int P = ly * N + lz;
         const cx<T>* src = fh + P;
         cx<T> y[K::NP];
 #pragma unroll
@@ -118,27 +213,27 @@ __device__ __forceinline__ void field_ifft(const cx<T>* __restrict__ fh, const c
         const cx<T> cyz = yzt[ly] * yzt[N + lz];
 #pragma unroll
         for (int mm = 0; mm < K::NP; ++mm) buf[(mm * N + ly) * K::ROW + lz] = y[mm] * cyz;
+        if (paired) {
+            const int ly2 = (N - ly) % N, lz2 = (N - lz) % N;
+            const cx<T> fn = src[(N / 2) * N * N];
+            const cx<T> delta = cx<T>{-nyq * fn.y, nyq * fn.x};
+            const cx<T> cyz2 = yzt[ly2] * yzt[N + lz2];
+#pragma unroll
+            for (int mm = 0; mm < K::NP; ++mm) {
+                const bool odd = ((CH * mm + c) & 1) != 0;
+                const cx<T> g = odd ? y[mm] - delta : y[mm] + delta;
+                buf[(mm * N + ly2) * K::ROW + lz2] = cx<T>{g.x, -g.y} * cyz2;
+            }
+        }
     }
     __syncthreads();
-    const int m = tid / N, r = tid % N;
-    {
-        cx<T> v[N];
-#pragma unroll
-        for (int ly = 0; ly < N; ++ly) v[ly] = buf[(m * N + ly) * K::ROW + r];
-        fft<N, +1>(v);
-#pragma unroll
-        for (int ny = 0; ny < N; ++ny) buf[(m * N + ny) * K::ROW + r] = v[ny];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int lz = 0; lz < N; ++lz) out[lz] = buf[(m * N + r) * K::ROW + lz];
-    fft<N, +1>(out);
+    yz_passes<T, N, CH, CZ, +1>(buf, cz, m, r, out);
     __syncthreads();
 }
 
-template <typename T, int N, int CH, int NT>
-__global__ __launch_bounds__(NT) void gain_kernel(GainArgs<T> a) {
-    using K = GainK<T, N, CH, NT>;
+template <typename T, int N, int CH, int CZ>
+__global__ __launch_bounds__((GainK<T, N, CH, CZ>::NT)) void gain_kernel(GainArgs<T> a) {
+    using K = GainK<T, N, CH, CZ>;
     __shared__ cx<T> buf[K::LDS];
     // Work items of one node are placed on one XCD (workgroups are dealt to the 8
     // XCDs round-robin), so that node's spectra stay in that XCD's L2.
@@ -158,44 +253,53 @@ __global__ __launch_bounds__(NT) void gain_kernel(GainArgs<T> a) {
     constexpr int64_t N3 = int64_t(N) * N * N;
     const cx<T>* fhi = a.fhat + (int64_t(b) * a.s + ci) * N3;
     const cx<T>* fhj = a.fhat + (int64_t(b) * a.s + cj) * N3;
+    const int tid = threadIdx.x;
+    const int cz = tid / K::NTC, u = tid % K::NTC;
+    const int m = u / N, r = u % N;
 
-    cx<T> S[N];
+    // Only Re(S_q) reaches the result: the radial operator multiplies DFT(S_q) by a
+    // real F that is even in k, so Re IDFT(F DFT(S)) = IDFT(F DFT(Re S)).
+    T S[K::NS];
 #pragma unroll
-    for (int n = 0; n < N; ++n) S[n] = cx<T>{T(0), T(0)};
+    for (int n = 0; n < K::NS; ++n) S[n] = T(0);
 
     for (int d = 0; d < ndir; ++d) {
         const int64_t base = (int64_t(doff + d) * a.nrho + q) * 2;
-        cx<T> A[N], B[N];
-        field_ifft<T, N, CH, NT>(fhi, a.kx + ((base + 0) * CH + c) * N, a.yz + (base + 0) * 2 * N, buf, A);
-        field_ifft<T, N, CH, NT>(fhj, a.kx + ((base + 1) * CH + c) * N, a.yz + (base + 1) * 2 * N, buf, B);
+        cx<T> A[K::NS], B[K::NS];
+        field_ifft<T, N, CH, CZ>(fhi, a.kx + ((base + 0) * CH + c) * N, a.yz + (base + 0) * 2 * N, a.nyq[base],
+                                 c, buf, cz, m, r, A);
+        field_ifft<T, N, CH, CZ>(fhj, a.kx + ((base + 1) * CH + c) * N, a.yz + (base + 1) * 2 * N,
+                                 a.nyq[base + 1], c, buf, cz, m, r, B);
 #pragma unroll
-        for (int n = 0; n < N; ++n) {
-            const cx<T> ab = A[n] * B[n];
-            S[n].x = fma(w, ab.x, S[n].x);
-            S[n].y = fma(w, ab.y, S[n].y);
-        }
+        for (int n = 0; n < K::NS; ++n) S[n] = fma(w, fma(A[n].x, B[n].x, -A[n].y * B[n].y), S[n]);
     }
 
-    // forward DFT of S_q: z in registers, y through LDS, then the chunk's part of x
-    const int tid = threadIdx.x;
-    const int m = tid / N, r = tid % N;
-    fft<N, -1>(S);
+    // forward DFT of Re S_q: z and y through LDS, then the chunk's part of x
 #pragma unroll
-    for (int kz = 0; kz < N; ++kz) buf[(m * N + r) * K::ROW + kz] = S[kz];
+    for (int j = 0; j < K::NS; ++j) buf[(m * N + r) * K::ROW + CZ * j + cz] = cx<T>{S[j], T(0)};
     __syncthreads();
     {
-        cx<T> v[N];
+        cx<T> v[K::NS];
+        with_group<CZ>(cz, [&](auto gg) {
+            split_fft<N, CZ, decltype(gg)::value, -1, 1>(buf + (m * N + r) * K::ROW, v);
+        });
+        __syncthreads();
 #pragma unroll
-        for (int ky = 0; ky < N; ++ky) v[ky] = buf[(m * N + ky) * K::ROW + r];
-        fft<N, -1>(v);
+        for (int j = 0; j < K::NS; ++j) buf[(m * N + r) * K::ROW + CZ * j + cz] = v[j];
+        __syncthreads();
+        with_group<CZ>(cz, [&](auto gg) {
+            split_fft<N, CZ, decltype(gg)::value, -1, K::ROW>(buf + (m * N) * K::ROW + r, v);
+        });
+        __syncthreads();
 #pragma unroll
-        for (int ky = 0; ky < N; ++ky) buf[(m * N + ky) * K::ROW + r] = v[ky];
+        for (int j = 0; j < K::NS; ++j) buf[(m * N + CZ * j + cz) * K::ROW + r] = v[j];
+        __syncthreads();
     }
-    __syncthreads();
     cx<T>* Pout = a.P + ((int64_t(b) * a.ncls + cl) * a.nrho + q) * N3 + int64_t(c) * (N3 / CH);
-#pragma unroll
+#pragma unroll 1
     for (int k = 0; k < K::PX; ++k) {
-        const int P = tid + k * NT;
+        const int P = tid + k * K::NT;
+        if (K::PX * K::NT != N * N && P >= N * N) break;
         const int ky = P / N, kz = P % N;
         cx<T> v[K::NP];
 #pragma unroll
@@ -405,7 +509,7 @@ hipError_t fft3d(cx<T>* data, const void* real_in, int64_t nfields, int sign, T 
 
 // ev (optional): 6 events recorded at the stage boundaries (start, after forward FFT,
 // after gain, after radial, after inverse FFTs, after combine).
-template <typename T, int N, int CH, int NT>
+template <typename T, int N, int CH, int CZ>
 hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, bool pairs, hipStream_t st,
                      hipEvent_t* ev) {
     auto mark = [&](int k) {
@@ -433,6 +537,7 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
     ga.P = P;
     ga.kx = reinterpret_cast<const cx<T>*>(dev + p.off_kx);
     ga.yz = reinterpret_cast<const cx<T>*>(dev + p.off_yz);
+    ga.nyq = reinterpret_cast<const T*>(dev + p.off_nyq);
     ga.cls = reinterpret_cast<const int*>(dev + p.off_cls);
     ga.wdir = reinterpret_cast<const T*>(dev + p.off_wdir);
     ga.s = p.s;
@@ -441,7 +546,7 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
     ga.nb = nb;
     const int64_t ipn = int64_t(ncls) * p.nrho * CH;
     const int64_t groups = ((nb + 7) / 8) * 8 * ipn;
-    gain_kernel<T, N, CH, NT><<<dim3(unsigned(groups)), dim3(NT), 0, st>>>(ga);
+    gain_kernel<T, N, CH, CZ><<<dim3(unsigned(groups)), dim3(GainK<T, N, CH, CZ>::NT), 0, st>>>(ga);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     mark(2);
 
@@ -482,12 +587,14 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
 template <typename T>
 hipError_t dispatch(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, bool pairs, hipStream_t st,
                     hipEvent_t* ev) {
+    constexpr bool dbl = sizeof(T) == 8;
     switch (p.N) {
-        case 16: return run_slice<T, 16, 1, 256>(p, f, Q, nb, ws, pairs, st, ev);
-        case 24: return run_slice<T, 24, 3, 192>(p, f, Q, nb, ws, pairs, st, ev);
-        case 32:
-            if constexpr (sizeof(T) == 4) return run_slice<T, 32, 4, 256>(p, f, Q, nb, ws, pairs, st, ev);
-            else return hipErrorInvalidValue;
+        case 16: return run_slice<T, 16, 1, 1>(p, f, Q, nb, ws, pairs, st, ev);
+        case 24: return run_slice<T, 24, 3, 2>(p, f, Q, nb, ws, pairs, st, ev);
+        case 32: return run_slice<T, 32, 4, 1>(p, f, Q, nb, ws, pairs, st, ev);
+        case 48:
+            if constexpr (dbl) return run_slice<T, 48, 12, 4>(p, f, Q, nb, ws, pairs, st, ev);
+            else return run_slice<T, 48, 6, 2>(p, f, Q, nb, ws, pairs, st, ev);
         default: return hipErrorInvalidValue;
     }
 }
@@ -495,13 +602,12 @@ hipError_t dispatch(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, bool
 }  // namespace
 
 bool gain_geometry(int N, int precision, GainGeometry* g) {
+    const bool dbl = precision == DGFS_FP64;
     switch (N) {
-        case 16: *g = {1, 256}; return true;
-        case 24: *g = {3, 192}; return true;
-        case 32:
-            if (precision != DGFS_FP32) return false;
-            *g = {4, 256};
-            return true;
+        case 16: *g = {1, 1}; return true;
+        case 24: *g = {3, 2}; return true;
+        case 32: *g = {4, 1}; return true;
+        case 48: *g = dbl ? GainGeometry{12, 4} : GainGeometry{6, 2}; return true;
         default: return false;
     }
 }

@@ -14,10 +14,11 @@ namespace dgfs {
 
 // Launch geometry of the fused gain kernel for one velocity resolution N:
 // CH   chunks of the output grid along x (each work item owns x-indices = c mod CH),
-// NT   threads per work item (one y/z pencil of the chunk per thread).
+// CZ   thread groups sharing each y/z pencil of the chunk (group g keeps the outputs
+//      with index = g mod CZ).
 struct GainGeometry {
     int CH;
-    int NT;
+    int CZ;
 };
 
 bool gain_geometry(int N, int precision, GainGeometry* g);
@@ -68,7 +69,7 @@ struct dgfs_plan {
     void* dev = nullptr;  // one block holding every table
     size_t dev_bytes = 0;
     // byte offsets of the tables in `dev`
-    size_t off_kx = 0, off_yz = 0, off_F = 0, off_G = 0, off_tw = 0, off_cls = 0, off_wdir = 0;
+    size_t off_kx = 0, off_yz = 0, off_nyq = 0, off_F = 0, off_G = 0, off_tw = 0, off_cls = 0, off_wdir = 0;
     size_t off_minv = 0;  // (s+4)^2 doubles, inverse Gram matrix of the invariants
 
     size_t elem() const { return precision == DGFS_FP64 ? sizeof(double) : sizeof(float); }

@@ -60,7 +60,8 @@ def test_check_problem_accepts_and_rejects():
     vss = [[(0.74, 1.4, 1.0)] * 2 for _ in range(2)]
     assert check_problem(m, 6.0, 32, 12, 16, vss) == DGFS_EUNSUPPORTED   # VSS not implemented
     assert check_problem(m, 6.0, 20, 12, 16, k) == DGFS_EUNSUPPORTED     # no kernels for N=20
-    assert check_problem(m, 6.0, 32, 12, 16, k, "f64") == DGFS_EUNSUPPORTED
+    assert check_problem(m, 6.0, 32, 12, 16, k, "f64") == DGFS_OK
+    assert check_problem(m, 6.0, 48, 24, 24, k) == DGFS_OK
     assert check_problem(m, 6.0, 32, 12, 16, k, L_species=(6.0, 1.0)) == DGFS_EUNSUPPORTED
 
 

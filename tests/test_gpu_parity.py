@@ -123,6 +123,33 @@ def test_three_species_N24(precision, tol):
     assert _rel(Q[0], ref) <= tol
 
 
+# ---------------------------------------------------------------- N = 48
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-5), ("f64", 1e-12)])
+def test_two_species_N48(precision, tol):
+    """N = 48 (the largest grid), masses (1, 2), M = 6, N_rho = 8, two nodes."""
+    _require_gpu()
+    print(f"[case] N=48 {precision}", flush=True)
+    rng = np.random.default_rng(48)
+    masses = (1.0, 2.0)
+    f = I.draw_bimaxwellian_batch(rng, 2, 2, 48, 6.0, masses, noise=1e-2)
+    if precision == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    Q = _run(_plan(masses, 48, 6.0, 6, 8, 0.74, precision), f)
+    prob = _oracle_problem(masses, 0.74, 6.0, 48, 6, 8)
+    for b in range(2):
+        assert _rel(Q[b], OS.collide(f[b], prob)) <= tol, b
+
+
+def test_two_species_N32_fp64():
+    _require_gpu()
+    print("[case] N=32 fp64", flush=True)
+    rng = np.random.default_rng(32)
+    masses = (1.0, 2.0)
+    f = I.draw_bimaxwellian_batch(rng, 1, 2, 32, 6.0, masses, noise=1e-2)
+    Q = _run(_plan(masses, 32, 6.0, 12, 8, 0.74, "f64"), f)
+    assert _rel(Q[0], OS.collide(f[0], _oracle_problem(masses, 0.74, 6.0, 32, 12, 8))) <= 1e-12
+
+
 # ------------------------------------------------- N = 32 slab workload (FP32)
 def _slab_inputs(batch, seed=2):
     rng = np.random.default_rng(seed)
