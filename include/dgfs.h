@@ -81,6 +81,10 @@ typedef struct {
                                         kernel[i*s+j] == kernel[j*s+i] (the cross-species
                                         conservation of Sec. 2, eq. consv, needs it) */
     int32_t precision;               /* DGFS_FP32 or DGFS_FP64 */
+    int32_t tile_ch, tile_cz;        /* gain-kernel geometry: x-chunks per field and thread
+                                        groups per y/z pencil; 0, 0 = the library's default
+                                        for (N, precision); other values must be one of
+                                        dgfs_tile_candidates (DGFS_EUNSUPPORTED otherwise) */
 } dgfs_problem;
 
 typedef struct dgfs_plan dgfs_plan;
@@ -120,6 +124,16 @@ dgfs_status dgfs_collide_timed(const dgfs_plan* plan, const void* f, void* Q, in
 dgfs_status dgfs_collide_pairs(const dgfs_plan* plan, const void* f, void* Q, int64_t batch,
                                void* workspace, size_t ws_bytes, void* stream);
 
+/* The plain per-point FP64 path, for comparison with dgfs_collide: the same
+ * discretised operator evaluated node by node with unfused kernels (for every ordered
+ * pair, radial point and all M directions: phase multiply, inverse 3-D FFTs, product
+ * accumulation; per radial point a forward FFT and the radial weighting; then the loss
+ * convolution), without the class sharing of the antipodal designs.  Needs an FP64 plan
+ * (DGFS_EUNSUPPORTED otherwise).  f, Q: device doubles [batch][s][N^3];
+ * ws_bytes >= dgfs_workspace_size(plan, 1). */
+dgfs_status dgfs_collide_plain(const dgfs_plan* plan, const double* f, double* Q, int64_t batch,
+                               void* workspace, size_t ws_bytes, void* stream);
+
 /* FP64 conservation correction (least-squares projection onto the collision
  * invariants of Sec. 2, eq. consv): with A the (s+4) x (s N^3) matrix of species
  * numbers, total momentum and total energy (rectangle rule, weight h^3 and m_i),
@@ -136,6 +150,38 @@ dgfs_status dgfs_conserve(const dgfs_plan* plan, const void* Q_raw, double* Q_ou
  * Any output pointer may be NULL.  No device is touched. */
 dgfs_status dgfs_pair_tables(const dgfs_problem* problem, int32_t i, int32_t j, double* info,
                              double* rho, double* w_rho, double* loss);
+
+/* Gain-kernel geometries compiled for (N, precision), as pairs (ch, cz) in
+ * pairs[2*k], pairs[2*k+1], k < *count <= max_pairs; the first is the default. */
+dgfs_status dgfs_tile_candidates(int32_t N, int32_t precision, int32_t* pairs, int32_t max_pairs,
+                                 int32_t* count);
+
+/* ---- uneven batches: several plans (e.g. different N) evaluated together ----------
+ * A group runs each plan's pipeline on its own stream, forked from and joined back to
+ * the caller's stream with events, so the hardware overlaps the N-classes; a group
+ * call can be captured once into a hipGraph and replayed with one launch.  The group
+ * owns its streams and events (created on the current device, default priority). */
+typedef struct dgfs_group dgfs_group;
+
+dgfs_status dgfs_group_create(const dgfs_plan* const* plans, int32_t nplans, dgfs_group** out);
+void dgfs_group_destroy(dgfs_group* group);
+
+/* Bytes of one workspace covering batch[k] nodes of every plan k in one pass. */
+dgfs_status dgfs_group_workspace_size(const dgfs_group* group, const int64_t* batch, size_t* bytes);
+
+/* For every plan k: Q[k] = collide(plan k, f[k], batch[k]) (same layout as dgfs_collide).
+ * The caller's stream waits for all of them.  Asynchronous. */
+dgfs_status dgfs_group_collide(dgfs_group* group, const void* const* f, void* const* Q,
+                               const int64_t* batch, void* workspace, size_t ws_bytes, void* stream);
+
+/* Capture dgfs_group_collide with these arguments on `stream` (a non-default stream)
+ * into a hipGraph, instantiate it and return the executable graph (hipGraphExec_t as
+ * void*) in *graph.  Nothing runs during capture. */
+dgfs_status dgfs_group_capture(dgfs_group* group, const void* const* f, void* const* Q,
+                               const int64_t* batch, void* workspace, size_t ws_bytes, void* stream,
+                               void** graph);
+dgfs_status dgfs_graph_launch(void* graph, void* stream);
+void dgfs_graph_destroy(void* graph);
 
 /* Host-side copy of the M-point design used by the plan, [M][3]. */
 dgfs_status dgfs_design(int32_t M, double* sigma);

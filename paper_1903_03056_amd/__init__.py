@@ -5,7 +5,10 @@ Q^i = sum_j Q^{ij}(f^i, f^j) for a batch of independent spatial points with hand
 HIP kernels; this package is its thin Python binding.
 """
 from .collision import (  # noqa: F401
+    CollisionGroup,
     CollisionPlan,
+    Graph,
+    tile_candidates,
     check_problem,
     design,
     pair_tables,

@@ -17,8 +17,10 @@ DGFS_FP32, DGFS_FP64 = 0, 1
 
 EXPORTED = (
     "dgfs_check_problem", "dgfs_plan_create", "dgfs_plan_destroy", "dgfs_workspace_size",
-    "dgfs_collide", "dgfs_collide_timed", "dgfs_collide_pairs", "dgfs_conserve", "dgfs_pair_tables", "dgfs_design",
-    "dgfs_status_string", "dgfs_last_error",
+    "dgfs_collide", "dgfs_collide_timed", "dgfs_collide_pairs", "dgfs_collide_plain", "dgfs_conserve", "dgfs_pair_tables", "dgfs_design",
+    "dgfs_status_string", "dgfs_last_error", "dgfs_tile_candidates", "dgfs_group_create", "dgfs_group_destroy",
+    "dgfs_group_workspace_size", "dgfs_group_collide", "dgfs_group_capture", "dgfs_graph_launch",
+    "dgfs_graph_destroy",
 )
 
 
@@ -37,6 +39,8 @@ class Problem(ctypes.Structure):
         ("n_rho", c_int32),
         ("kernel", POINTER(PairKernel)),
         ("precision", c_int32),
+        ("tile_ch", c_int32),
+        ("tile_cz", c_int32),
     ]
 
 
@@ -62,7 +66,7 @@ def load() -> ctypes.CDLL:
     lib.dgfs_plan_destroy.argtypes = [c_void_p]
     lib.dgfs_plan_destroy.restype = None
     lib.dgfs_workspace_size.argtypes = [c_void_p, c_int64, POINTER(c_size_t)]
-    for name in ("dgfs_collide", "dgfs_collide_pairs"):
+    for name in ("dgfs_collide", "dgfs_collide_pairs", "dgfs_collide_plain"):
         getattr(lib, name).argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_size_t, c_void_p]
     lib.dgfs_collide_timed.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_size_t, c_void_p,
                                        POINTER(ctypes.c_float)]
@@ -70,12 +74,25 @@ def load() -> ctypes.CDLL:
     lib.dgfs_pair_tables.argtypes = [POINTER(Problem), c_int32, c_int32, POINTER(c_double), POINTER(c_double),
                                      POINTER(c_double), POINTER(c_double)]
     lib.dgfs_design.argtypes = [c_int32, POINTER(c_double)]
+    lib.dgfs_tile_candidates.argtypes = [c_int32, c_int32, POINTER(c_int32), c_int32, POINTER(c_int32)]
+    lib.dgfs_group_create.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_void_p)]
+    lib.dgfs_group_destroy.argtypes = [c_void_p]
+    lib.dgfs_group_destroy.restype = None
+    lib.dgfs_group_workspace_size.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_size_t)]
+    lib.dgfs_group_collide.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_int64), c_void_p,
+                                       c_size_t, c_void_p]
+    lib.dgfs_group_capture.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_int64), c_void_p,
+                                       c_size_t, c_void_p, POINTER(c_void_p)]
+    lib.dgfs_graph_launch.argtypes = [c_void_p, c_void_p]
+    lib.dgfs_graph_destroy.argtypes = [c_void_p]
+    lib.dgfs_graph_destroy.restype = None
     lib.dgfs_status_string.argtypes = [c_int32]
     lib.dgfs_status_string.restype = ctypes.c_char_p
     lib.dgfs_last_error.argtypes = []
     lib.dgfs_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
-        if name not in ("dgfs_plan_destroy", "dgfs_status_string", "dgfs_last_error"):
+        if name not in ("dgfs_plan_destroy", "dgfs_status_string", "dgfs_last_error", "dgfs_group_destroy",
+                        "dgfs_graph_destroy"):
             getattr(lib, name).restype = c_int32
     _lib = lib
     return lib

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libdgfs.so")
 
-SOURCES = ["api.cpp", "precompute.cpp", "kernels.hip"]
+SOURCES = ["api.cpp", "precompute.cpp", "kernels.hip", "plain.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -33,7 +33,7 @@ def _precision_code(precision) -> int:
 class _ProblemHolder:
     """Keeps the ctypes arrays alive as long as the Problem struct refers to them."""
 
-    def __init__(self, masses, L, N, M, n_rho, kernel, precision, L_species=None):
+    def __init__(self, masses, L, N, M, n_rho, kernel, precision, L_species=None, tile=None):
         s = len(masses)
         self.mass = (c_double * s)(*masses)
         self.kern = (PairKernel * (s * s))()
@@ -44,7 +44,8 @@ class _ProblemHolder:
         self.Ls = (c_double * s)(*L_species) if L_species is not None else None
         self.problem = Problem(s=s, mass=self.mass, L=float(L),
                                L_species=self.Ls if self.Ls is not None else None,
-                               N=N, M=M, n_rho=n_rho, kernel=self.kern, precision=_precision_code(precision))
+                               N=N, M=M, n_rho=n_rho, kernel=self.kern, precision=_precision_code(precision),
+                               tile_ch=int(tile[0]) if tile else 0, tile_cz=int(tile[1]) if tile else 0)
 
 
 def vhs_kernel(masses, omega, alpha: float = 1.0, kn0: float = 1.0):
@@ -53,10 +54,19 @@ def vhs_kernel(masses, omega, alpha: float = 1.0, kn0: float = 1.0):
             for i in range(s)]
 
 
-def check_problem(masses, L, N, M, n_rho, kernel, precision="f32", L_species=None) -> int:
+def check_problem(masses, L, N, M, n_rho, kernel, precision="f32", L_species=None, tile=None) -> int:
     """Host-side validation; returns the dgfs status code (0 = ok)."""
-    h = _ProblemHolder(masses, L, N, M, n_rho, kernel, precision, L_species)
+    h = _ProblemHolder(masses, L, N, M, n_rho, kernel, precision, L_species, tile=tile)
     return load().dgfs_check_problem(ctypes.byref(h.problem))
+
+
+def tile_candidates(N: int, precision="f32"):
+    """Gain-kernel geometries (ch, cz) compiled for (N, precision); the first is the default."""
+    lib = load()
+    buf = (ctypes.c_int32 * 32)()
+    n = ctypes.c_int32()
+    check(lib.dgfs_tile_candidates(N, _precision_code(precision), buf, 16, ctypes.byref(n)), "dgfs_tile_candidates")
+    return [(buf[2 * k], buf[2 * k + 1]) for k in range(n.value)]
 
 
 def design(M: int) -> np.ndarray:
@@ -87,7 +97,7 @@ class CollisionPlan:
     prefactor of eqs. (Kn)/(NVSS) with Kn0 = ``kn0``."""
 
     def __init__(self, masses, N: int, L: float, M: int, n_rho: int, omega: float | None = None,
-                 kernel=None, precision="f32", kn0: float = 1.0):
+                 kernel=None, precision="f32", kn0: float = 1.0, tile=None):
         import torch  # noqa: F401  (initialises the HIP runtime the library shares)
 
         if kernel is None:
@@ -98,7 +108,11 @@ class CollisionPlan:
         self.s, self.N, self.L, self.M, self.n_rho = len(masses), N, float(L), M, n_rho
         self.kernel = kernel
         self.precision = _precision_code(precision)
-        self._holder = _ProblemHolder(self.masses, L, N, M, n_rho, kernel, precision)
+        if tile == "auto":
+            from .autotune import best_tile
+            tile = best_tile(self.masses, N, L, M, n_rho, kernel, precision)
+        self.tile = tuple(tile) if tile else None
+        self._holder = _ProblemHolder(self.masses, L, N, M, n_rho, kernel, precision, tile=self.tile)
         self._lib = load()
         handle = c_void_p()
         check(self._lib.dgfs_plan_create(ctypes.byref(self._holder.problem), ctypes.byref(handle)),
@@ -183,6 +197,19 @@ class CollisionPlan:
                                            c_void_p(st.cuda_stream), ms), "dgfs_collide_timed")
         return out, list(ms)
 
+    def collide_plain(self, f, out=None, workspace=None, stream=None):
+        """The plain per-point FP64 path (dgfs_collide_plain); FP64 plans only."""
+        import torch
+        self._check_f(f)
+        if out is None:
+            out = torch.empty(f.shape, dtype=f.dtype, device=f.device)
+        ws = workspace if workspace is not None else self.workspace(1, f.device)
+        st = stream if stream is not None else torch.cuda.current_stream(f.device)
+        check(self._lib.dgfs_collide_plain(self._plan, c_void_p(f.data_ptr()), c_void_p(out.data_ptr()),
+                                           f.shape[0], c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                           c_void_p(st.cuda_stream)), "dgfs_collide_plain")
+        return out
+
     def conserve(self, Q, out=None, stream=None):
         """FP64 conservation projection of a raw collision result (same layout as f)."""
         import torch
@@ -193,3 +220,96 @@ class CollisionPlan:
         check(self._lib.dgfs_conserve(self._plan, c_void_p(Q.data_ptr()), c_void_p(out.data_ptr()), Q.shape[0],
                                       c_void_p(st.cuda_stream)), "dgfs_conserve")
         return out
+
+
+class CollisionGroup:
+    """Several plans (e.g. different N) evaluated together: each plan's pipeline runs on
+    its own stream forked from the caller's stream, and the whole call can be captured
+    once into a hipGraph (``capture``) and replayed with a single launch."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        self._lib = load()
+        arr = (c_void_p * len(self.plans))(*[p._plan for p in self.plans])
+        handle = c_void_p()
+        check(self._lib.dgfs_group_create(arr, len(self.plans), ctypes.byref(handle)), "dgfs_group_create")
+        self._group = handle
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_group", None):
+            self._lib.dgfs_group_destroy(self._group)
+            self._group = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, batches) -> int:
+        b = (ctypes.c_int64 * len(self.plans))(*batches)
+        n = c_size_t()
+        check(self._lib.dgfs_group_workspace_size(self._group, b, ctypes.byref(n)), "dgfs_group_workspace_size")
+        return n.value
+
+    def _args(self, fs, outs, workspace):
+        import torch
+        for p, f in zip(self.plans, fs):
+            p._check_f(f)
+        if outs is None:
+            outs = [torch.empty_like(f) for f in fs]
+        batches = [f.shape[0] for f in fs]
+        need = self.workspace_bytes(batches)
+        ws = workspace
+        if ws is None:
+            if self._ws is None or self._ws.numel() < need:
+                self._ws = torch.empty(need, dtype=torch.uint8, device=fs[0].device)
+            ws = self._ws
+        fa = (c_void_p * len(fs))(*[f.data_ptr() for f in fs])
+        qa = (c_void_p * len(fs))(*[q.data_ptr() for q in outs])
+        ba = (ctypes.c_int64 * len(fs))(*batches)
+        return outs, ws, fa, qa, ba
+
+    def collide(self, fs, outs=None, workspace=None, stream=None):
+        import torch
+        outs, ws, fa, qa, ba = self._args(fs, outs, workspace)
+        st = stream if stream is not None else torch.cuda.current_stream(fs[0].device)
+        check(self._lib.dgfs_group_collide(self._group, fa, qa, ba, c_void_p(ws.data_ptr()),
+                                           ws.numel() * ws.element_size(), c_void_p(st.cuda_stream)),
+              "dgfs_group_collide")
+        return outs
+
+    def capture(self, fs, outs=None, workspace=None, stream=None):
+        """Capture collide(fs) into an executable graph; returns (graph, outs).  The
+        buffers must stay alive and in place while the graph is used."""
+        import torch
+        outs, ws, fa, qa, ba = self._args(fs, outs, workspace)
+        st = stream if stream is not None else torch.cuda.Stream(fs[0].device)
+        g = c_void_p()
+        check(self._lib.dgfs_group_capture(self._group, fa, qa, ba, c_void_p(ws.data_ptr()),
+                                           ws.numel() * ws.element_size(), c_void_p(st.cuda_stream),
+                                           ctypes.byref(g)), "dgfs_group_capture")
+        return Graph(self._lib, g, st, keep=(fs, outs, ws)), outs
+
+
+class Graph:
+    """An instantiated hipGraph of a group call."""
+
+    def __init__(self, lib, handle, stream, keep):
+        self._lib, self._g, self.stream, self._keep = lib, handle, stream, keep
+
+    def launch(self, stream=None):
+        st = stream if stream is not None else self.stream
+        check(self._lib.dgfs_graph_launch(self._g, c_void_p(st.cuda_stream)), "dgfs_graph_launch")
+
+    def close(self):
+        if getattr(self, "_g", None):
+            self._lib.dgfs_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -62,6 +62,13 @@ dgfs_status check(const dgfs_problem* p) {
     dgfs::GainGeometry g;
     if (!dgfs::gain_geometry(p->N, p->precision, &g))
         return fail(DGFS_EUNSUPPORTED, "no kernel for this N at this precision");
+    if (p->tile_ch != 0 || p->tile_cz != 0) {
+        dgfs::GainGeometry cand[16];
+        const int n = dgfs::tile_candidates(p->N, p->precision, cand, 16);
+        bool ok = false;
+        for (int k = 0; k < n; ++k) ok = ok || (cand[k].CH == p->tile_ch && cand[k].CZ == p->tile_cz);
+        if (!ok) return fail(DGFS_EUNSUPPORTED, "tile geometry not compiled for this N and precision");
+    }
     return DGFS_OK;
 }
 
@@ -286,6 +293,36 @@ void build_tables(dgfs_plan& P, std::vector<char>& blob) {
         push_int(blob, S.off_lterms, S.lterms);
     }
 
+    // ---------------- plain per-point FP64 path: per ordered pair, all M directions
+    if (P.precision == DGFS_FP64) {
+        std::vector<std::complex<double>> ph(size_t(s) * s * nrho * P.M * 2 * 3 * N);
+        std::vector<double> pF(size_t(s) * s * nrho * K2);
+        for (int i = 0; i < s; ++i)
+            for (int j = 0; j < s; ++j) {
+                const int pr = i * s + j;
+                const dgfs::PairParams& pp = P.pair[pr];
+                for (int q = 0; q < nrho; ++q) {
+                    for (int d = 0; d < P.M; ++d)
+                        for (int fld = 0; fld < 2; ++fld) {
+                            const double sgn = fld == 0 ? 1.0 : -1.0;
+                            const double coef = fld == 0 ? pp.a : pp.b;
+                            for (int dim = 0; dim < 3; ++dim) {
+                                const double th = sgn * kPi * pp.rho[q] * coef * P.sigma[3 * d + dim] / L;
+                                for (int jj = 0; jj < N; ++jj)
+                                    ph[((((size_t(pr) * nrho + q) * P.M + d) * 2 + fld) * 3 + dim) * N + jj] =
+                                        std::polar(1.0, th * signed_mode(jj, N));
+                            }
+                        }
+                    for (int k2 = 0; k2 < K2; ++k2)
+                        pF[(size_t(pr) * nrho + q) * K2 + k2] =
+                            pp.wrho[q] * dgfs::pre::kernel_mode(std::sqrt(double(k2)), pp.rho[q], pp.a, pp.gamma,
+                                                                pp.C, L) / n3;
+                }
+            }
+        push_cplx<double>(blob, P.off_plain_ph, ph);
+        push_double(blob, P.off_plain_F, pF);
+    }
+
     // ---------------- conservation: inverse Gram matrix of the s+4 invariants, masses
     {
         const int nr = s + 4;
@@ -379,6 +416,7 @@ dgfs_status dgfs_plan_create(const dgfs_problem* problem, dgfs_plan** out) {
     P->L = problem->L;
     P->mass.assign(problem->mass, problem->mass + problem->s);
     dgfs::gain_geometry(P->N, P->precision, &P->geo);
+    if (problem->tile_ch != 0 || problem->tile_cz != 0) P->geo = dgfs::GainGeometry{problem->tile_ch, problem->tile_cz};
     dgfs::pre::design(P->M, P->sigma);
     P->antipodal = dgfs::pre::antipodal(P->sigma);
     P->K2 = 3 * (P->N / 2) * (P->N / 2) + 1;
@@ -435,8 +473,9 @@ void dgfs_plan_destroy(dgfs_plan* plan) {
 dgfs_status dgfs_workspace_size(const dgfs_plan* plan, int64_t batch, size_t* bytes) {
     if (!plan || !bytes) return fail(DGFS_EINVAL, "plan and bytes are required");
     if (batch < 1) return fail(DGFS_EINVAL, "batch must be >= 1");
-    // the pair-resolved mode needs the larger slot set; size for it
-    *bytes = plan->ws_per_node(true) * size_t(batch) + 4 * 256;
+    // the pair-resolved mode needs the larger slot set; size for it (and at least what
+    // the plain FP64 path needs for one node)
+    *bytes = std::max(plan->ws_per_node(true) * size_t(batch) + 4 * 256, dgfs::plain_ws_bytes(*plan) + 256);
     return DGFS_OK;
 }
 
@@ -503,6 +542,20 @@ dgfs_status dgfs_collide_pairs(const dgfs_plan* plan, const void* f, void* Q, in
     return collide_impl(plan, f, Q, batch, workspace, ws_bytes, stream, true, nullptr);
 }
 
+dgfs_status dgfs_collide_plain(const dgfs_plan* plan, const double* f, double* Q, int64_t batch, void* workspace,
+                               size_t ws_bytes, void* stream) {
+    if (!plan) return fail(DGFS_EINVAL, "plan is NULL");
+    if (plan->precision != DGFS_FP64) return fail(DGFS_EUNSUPPORTED, "the plain path needs an FP64 plan");
+    if (batch < 0) return fail(DGFS_EINVAL, "batch must be >= 0");
+    if (batch == 0) return DGFS_OK;
+    if (!f || !Q || !workspace) return fail(DGFS_EINVAL, "f, Q and workspace are required");
+    if (static_cast<const void*>(f) == static_cast<void*>(Q)) return fail(DGFS_EINVAL, "f and Q must not overlap");
+    if (ws_bytes < dgfs::plain_ws_bytes(*plan)) return fail(DGFS_ENOMEM, "workspace smaller than one node");
+    hipError_t e = dgfs::launch_collide_plain(*plan, f, Q, batch, workspace, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(DGFS_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return DGFS_OK;
+}
+
 dgfs_status dgfs_conserve(const dgfs_plan* plan, const void* Q_raw, double* Q_out, int64_t batch, void* stream) {
     if (!plan) return fail(DGFS_EINVAL, "plan is NULL");
     if (batch < 0) return fail(DGFS_EINVAL, "batch must be >= 0");
@@ -513,6 +566,148 @@ dgfs_status dgfs_conserve(const dgfs_plan* plan, const void* Q_raw, double* Q_ou
     hipError_t e = dgfs::launch_conserve(*plan, Q_raw, Q_out, batch, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail(DGFS_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
     return DGFS_OK;
+}
+
+dgfs_status dgfs_tile_candidates(int32_t N, int32_t precision, int32_t* pairs, int32_t max_pairs, int32_t* count) {
+    if (!count) return fail(DGFS_EINVAL, "count is required");
+    dgfs::GainGeometry cand[16];
+    const int n = dgfs::tile_candidates(N, precision, cand, 16);
+    *count = 0;
+    for (int k = 0; k < n && k < max_pairs; ++k) {
+        if (pairs) {
+            pairs[2 * k] = cand[k].CH;
+            pairs[2 * k + 1] = cand[k].CZ;
+        }
+        *count = k + 1;
+    }
+    return DGFS_OK;
+}
+
+// ------------------------------------------------------------------- groups
+struct dgfs_group {
+    std::vector<const dgfs_plan*> plans;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> join;
+    hipEvent_t fork = nullptr;
+    int device = 0;
+};
+
+static size_t group_offset(const dgfs_group* g, const int64_t* batch, size_t k) {
+    size_t off = 0;
+    for (size_t i = 0; i < k; ++i) {
+        size_t b = 0;
+        dgfs_workspace_size(g->plans[i], std::max<int64_t>(batch[i], 1), &b);
+        off += (b + 255) & ~size_t(255);
+    }
+    return off;
+}
+
+dgfs_status dgfs_group_create(const dgfs_plan* const* plans, int32_t nplans, dgfs_group** out) {
+    if (!plans || !out || nplans < 1 || nplans > 64) return fail(DGFS_EINVAL, "need 1..64 plans and out");
+    auto* g = new dgfs_group();
+    hipGetDevice(&g->device);
+    for (int k = 0; k < nplans; ++k) {
+        if (!plans[k]) {
+            dgfs_group_destroy(g);
+            return fail(DGFS_EINVAL, "NULL plan in group");
+        }
+        g->plans.push_back(plans[k]);
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            if (st) hipStreamDestroy(st);
+            dgfs_group_destroy(g);
+            return fail(DGFS_EDEVICE, "stream/event creation failed");
+        }
+        g->streams.push_back(st);
+        g->join.push_back(ev);
+    }
+    if (hipEventCreateWithFlags(&g->fork, hipEventDisableTiming) != hipSuccess) {
+        dgfs_group_destroy(g);
+        return fail(DGFS_EDEVICE, "event creation failed");
+    }
+    *out = g;
+    return DGFS_OK;
+}
+
+void dgfs_group_destroy(dgfs_group* g) {
+    if (!g) return;
+    for (auto st : g->streams)
+        if (st) hipStreamDestroy(st);
+    for (auto ev : g->join)
+        if (ev) hipEventDestroy(ev);
+    if (g->fork) hipEventDestroy(g->fork);
+    delete g;
+}
+
+dgfs_status dgfs_group_workspace_size(const dgfs_group* g, const int64_t* batch, size_t* bytes) {
+    if (!g || !batch || !bytes) return fail(DGFS_EINVAL, "group, batch and bytes are required");
+    for (size_t k = 0; k < g->plans.size(); ++k)
+        if (batch[k] < 0) return fail(DGFS_EINVAL, "batch must be >= 0");
+    *bytes = group_offset(g, batch, g->plans.size());
+    return DGFS_OK;
+}
+
+dgfs_status dgfs_group_collide(dgfs_group* g, const void* const* f, void* const* Q, const int64_t* batch,
+                               void* ws, size_t ws_bytes, void* stream) {
+    if (!g || !f || !Q || !batch || !ws) return fail(DGFS_EINVAL, "group, f, Q, batch and workspace are required");
+    size_t need = 0;
+    dgfs_status st = dgfs_group_workspace_size(g, batch, &need);
+    if (st != DGFS_OK) return st;
+    if (ws_bytes < need) return fail(DGFS_ENOMEM, "group workspace too small");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(DGFS_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t main = static_cast<hipStream_t>(stream);
+    if (hipEventRecord(g->fork, main) != hipSuccess) return fail(DGFS_EDEVICE, "hipEventRecord failed");
+    for (size_t k = 0; k < g->plans.size(); ++k) {
+        if (batch[k] == 0) continue;
+        if (hipStreamWaitEvent(g->streams[k], g->fork, 0) != hipSuccess)
+            return fail(DGFS_EDEVICE, "hipStreamWaitEvent failed");
+        const size_t off = group_offset(g, batch, k);
+        size_t b = 0;
+        dgfs_workspace_size(g->plans[k], batch[k], &b);
+        st = collide_impl(g->plans[k], f[k], Q[k], batch[k], static_cast<char*>(ws) + off, b, g->streams[k], false,
+                          nullptr);
+        if (st != DGFS_OK) return st;
+        if (hipEventRecord(g->join[k], g->streams[k]) != hipSuccess ||
+            hipStreamWaitEvent(main, g->join[k], 0) != hipSuccess)
+            return fail(DGFS_EDEVICE, "join failed");
+    }
+    return DGFS_OK;
+}
+
+dgfs_status dgfs_group_capture(dgfs_group* g, const void* const* f, void* const* Q, const int64_t* batch, void* ws,
+                               size_t ws_bytes, void* stream, void** graph) {
+    if (!graph) return fail(DGFS_EINVAL, "graph is required");
+    if (!stream) return fail(DGFS_EINVAL, "capture needs a non-default stream");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(DGFS_EDEVICE, "hipStreamBeginCapture failed");
+    dgfs_status rc = dgfs_group_collide(g, f, Q, batch, ws, ws_bytes, stream);
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &gr);
+    if (rc != DGFS_OK) {
+        if (gr) hipGraphDestroy(gr);
+        return rc;
+    }
+    if (e != hipSuccess || !gr) return fail(DGFS_EDEVICE, "hipStreamEndCapture failed");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+    hipGraphDestroy(gr);
+    if (e != hipSuccess) return fail(DGFS_EDEVICE, "hipGraphInstantiate failed");
+    *graph = exec;
+    return DGFS_OK;
+}
+
+dgfs_status dgfs_graph_launch(void* graph, void* stream) {
+    if (!graph) return fail(DGFS_EINVAL, "graph is NULL");
+    if (hipGraphLaunch(static_cast<hipGraphExec_t>(graph), static_cast<hipStream_t>(stream)) != hipSuccess)
+        return fail(DGFS_EDEVICE, "hipGraphLaunch failed");
+    return DGFS_OK;
+}
+
+void dgfs_graph_destroy(void* graph) {
+    if (graph) hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph));
 }
 
 const char* dgfs_status_string(dgfs_status status) {

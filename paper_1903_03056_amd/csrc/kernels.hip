@@ -22,45 +22,10 @@
 #include <cstdint>
 
 #include "fft.hpp"
+#include "passes.hpp"
 #include "plan.hpp"
 
 namespace dgfs {
-
-// ============================================================ pencil FFT passes
-// One thread transforms one pencil of a batch of N^3 fields along AXIS (0 = x,
-// stride N^2; 1 = y, stride N; 2 = z, stride 1).  In place when in == out.
-template <typename T, int N, int AXIS, int SIGN, bool REAL_IN>
-__global__ __launch_bounds__(256) void fft_pass_kernel(const void* __restrict__ in, cx<T>* out,
-                                                       int64_t npencils, T scale) {
-    const int64_t pid = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (pid >= npencils) return;
-    constexpr int64_t N2 = int64_t(N) * N, N3 = N2 * N;
-    const int64_t field = pid / N2;
-    const int r = int(pid - field * N2);
-    int64_t base, stride;
-    if constexpr (AXIS == 0) {
-        base = field * N3 + r;
-        stride = N2;
-    } else if constexpr (AXIS == 1) {
-        base = field * N3 + int64_t(r / N) * N2 + (r % N);
-        stride = N;
-    } else {
-        base = field * N3 + int64_t(r) * N;
-        stride = 1;
-    }
-    cx<T> v[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        if constexpr (REAL_IN) {
-            v[k] = cx<T>{static_cast<const T*>(in)[base + k * stride], T(0)};
-        } else {
-            v[k] = static_cast<const cx<T>*>(in)[base + k * stride];
-        }
-    }
-    fft<N, SIGN>(v);
-#pragma unroll
-    for (int k = 0; k < N; ++k) out[base + k * stride] = scale * v[k];
-}
 
 // ================================================================ gain kernel
 // Geometry of one work item: the x-chunk c (x-indices = c mod CH, NP = N/CH of them)
@@ -490,23 +455,6 @@ namespace {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-template <typename T, int N>
-hipError_t fft3d(cx<T>* data, const void* real_in, int64_t nfields, int sign, T scale, hipStream_t st) {
-    const int64_t np = nfields * N * N;
-    const dim3 grid(unsigned((np + 255) / 256)), block(256);
-    if (sign < 0) {
-        // forward from real input: z (real -> complex), y, x (with scale)
-        fft_pass_kernel<T, N, 2, -1, true><<<grid, block, 0, st>>>(real_in, data, np, T(1));
-        fft_pass_kernel<T, N, 1, -1, false><<<grid, block, 0, st>>>(data, data, np, T(1));
-        fft_pass_kernel<T, N, 0, -1, false><<<grid, block, 0, st>>>(data, data, np, scale);
-    } else {
-        fft_pass_kernel<T, N, 0, +1, false><<<grid, block, 0, st>>>(data, data, np, T(1));
-        fft_pass_kernel<T, N, 1, +1, false><<<grid, block, 0, st>>>(data, data, np, T(1));
-        fft_pass_kernel<T, N, 2, +1, false><<<grid, block, 0, st>>>(data, data, np, scale);
-    }
-    return hipGetLastError();
-}
-
 // ev (optional): 6 events recorded at the stage boundaries (start, after forward FFT,
 // after gain, after radial, after inverse FFTs, after combine).
 template <typename T, int N, int CH, int CZ>
@@ -584,33 +532,48 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
     return hipSuccess;
 }
 
+// Compiled gain-kernel geometries (CH, CZ) per N and precision; the first is the default.
+constexpr int kTilesF32[][3] = {{16, 1, 1}, {16, 1, 2}, {16, 2, 1}, {24, 3, 2}, {24, 3, 4}, {24, 3, 1},
+                                {32, 4, 1}, {32, 4, 2}, {32, 2, 1}, {48, 6, 2}, {48, 12, 4}, {48, 12, 2}};
+constexpr int kTilesF64[][3] = {{16, 1, 1}, {24, 3, 2}, {32, 4, 2}, {48, 12, 4}};
+
 template <typename T>
 hipError_t dispatch(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, bool pairs, hipStream_t st,
                     hipEvent_t* ev) {
-    constexpr bool dbl = sizeof(T) == 8;
-    switch (p.N) {
-        case 16: return run_slice<T, 16, 1, 1>(p, f, Q, nb, ws, pairs, st, ev);
-        case 24: return run_slice<T, 24, 3, 2>(p, f, Q, nb, ws, pairs, st, ev);
-        case 32: return run_slice<T, 32, 4, 1>(p, f, Q, nb, ws, pairs, st, ev);
-        case 48:
-            if constexpr (dbl) return run_slice<T, 48, 12, 4>(p, f, Q, nb, ws, pairs, st, ev);
-            else return run_slice<T, 48, 6, 2>(p, f, Q, nb, ws, pairs, st, ev);
-        default: return hipErrorInvalidValue;
+    const int key = p.N * 10000 + p.geo.CH * 100 + p.geo.CZ;
+#define DGFS_TILE(n, ch, cz) \
+    case n * 10000 + ch * 100 + cz: return run_slice<T, n, ch, cz>(p, f, Q, nb, ws, pairs, st, ev);
+    if constexpr (sizeof(T) == 4) {
+        switch (key) {
+            DGFS_TILE(16, 1, 1) DGFS_TILE(16, 1, 2) DGFS_TILE(16, 2, 1)
+            DGFS_TILE(24, 3, 2) DGFS_TILE(24, 3, 4) DGFS_TILE(24, 3, 1)
+            DGFS_TILE(32, 4, 1) DGFS_TILE(32, 4, 2) DGFS_TILE(32, 2, 1)
+            DGFS_TILE(48, 6, 2) DGFS_TILE(48, 12, 4) DGFS_TILE(48, 12, 2)
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (key) {
+            DGFS_TILE(16, 1, 1) DGFS_TILE(24, 3, 2) DGFS_TILE(32, 4, 2) DGFS_TILE(48, 12, 4)
+            default: return hipErrorInvalidValue;
+        }
     }
+#undef DGFS_TILE
 }
 
 }  // namespace
 
-bool gain_geometry(int N, int precision, GainGeometry* g) {
-    const bool dbl = precision == DGFS_FP64;
-    switch (N) {
-        case 16: *g = {1, 1}; return true;
-        case 24: *g = {3, 2}; return true;
-        case 32: *g = {4, 1}; return true;
-        case 48: *g = dbl ? GainGeometry{12, 4} : GainGeometry{6, 2}; return true;
-        default: return false;
-    }
+int tile_candidates(int N, int precision, GainGeometry* out, int max) {
+    int n = 0;
+    auto scan = [&](const auto& tab) {
+        for (const auto& t : tab)
+            if (t[0] == N && n < max) out[n++] = GainGeometry{t[1], t[2]};
+    };
+    if (precision == DGFS_FP64) scan(kTilesF64);
+    else scan(kTilesF32);
+    return n;
 }
+
+bool gain_geometry(int N, int precision, GainGeometry* g) { return tile_candidates(N, precision, g, 1) == 1; }
 
 hipError_t launch_collide(const dgfs_plan& p, const void* f, void* Q, int64_t nb, void* ws, bool pairs,
                           hipStream_t st, hipEvent_t* ev) {

@@ -21,7 +21,8 @@ struct GainGeometry {
     int CZ;
 };
 
-bool gain_geometry(int N, int precision, GainGeometry* g);
+bool gain_geometry(int N, int precision, GainGeometry* g);            // the default
+int tile_candidates(int N, int precision, GainGeometry* out, int max);  // compiled geometries
 
 // One "gain class": the S_q field sum_p w A_p B_p with A = f^i shifted by +a rho sigma_p,
 // B = f^j shifted by -b rho sigma_p.  With an antipodal design one class serves both
@@ -71,6 +72,8 @@ struct dgfs_plan {
     // byte offsets of the tables in `dev`
     size_t off_kx = 0, off_yz = 0, off_nyq = 0, off_F = 0, off_G = 0, off_tw = 0, off_cls = 0, off_wdir = 0;
     size_t off_minv = 0;  // (s+4)^2 doubles, inverse Gram matrix of the invariants
+    // plain per-point FP64 path (FP64 plans only): phases [s*s][nrho][M][2][3][N], F [s*s][nrho][K2]
+    size_t off_plain_ph = 0, off_plain_F = 0;
 
     size_t elem() const { return precision == DGFS_FP64 ? sizeof(double) : sizeof(float); }
     size_t n3() const { return size_t(N) * N * N; }
@@ -85,4 +88,8 @@ hipError_t launch_collide(const dgfs_plan& p, const void* f, void* Q, int64_t nb
                           bool pairs, hipStream_t stream, hipEvent_t* ev);
 hipError_t launch_conserve(const dgfs_plan& p, const void* Q, double* out, int64_t nb,
                            hipStream_t stream);
+// Plain per-point FP64 path (plain.hip).
+size_t plain_ws_bytes(const dgfs_plan& p);
+hipError_t launch_collide_plain(const dgfs_plan& p, const double* f, double* Q, int64_t nb, void* ws,
+                                hipStream_t stream);
 }  // namespace dgfs

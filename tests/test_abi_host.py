@@ -106,3 +106,19 @@ def test_host_tables_match_oracle(masses, omega, L, N, nrho):
             scale = np.abs(ref).max()
             assert np.abs(t["loss_by_k2"] - ref).max() <= 1e-13 * scale
             assert t["ndir"] == (6 if i == j else 12)
+
+
+def test_tile_candidates_and_validation():
+    from paper_1903_03056_amd import check_problem, tile_candidates
+    from paper_1903_03056_amd._lib import DGFS_EUNSUPPORTED, DGFS_OK
+    for N in (16, 24, 32, 48):
+        c32 = tile_candidates(N, "f32")
+        c64 = tile_candidates(N, "f64")
+        assert len(c32) >= 1 and len(c64) >= 1
+        for ch, cz in c32:
+            assert N % ch == 0 and N % cz == 0 and ((N // ch) * N) % 64 == 0
+    m = (1.0, 2.0)
+    k = _kern(m, 0.74)
+    for tile in tile_candidates(32, "f32"):
+        assert check_problem(m, 6.0, 32, 12, 16, k, tile=tile) == DGFS_OK
+    assert check_problem(m, 6.0, 32, 12, 16, k, tile=(3, 1)) == DGFS_EUNSUPPORTED

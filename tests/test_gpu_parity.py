@@ -218,6 +218,117 @@ def test_empty_batch_and_errors():
     assert float(z.abs().max()) == 0.0
 
 
+# -------------------------------------------- tiles, uneven groups, graphs
+@pytest.mark.parametrize("N,M,nrho", [(32, 12, 16), (48, 6, 8), (24, 12, 12), (16, 6, 8)])
+def test_every_tile_geometry_matches_oracle(N, M, nrho):
+    """Each compiled gain-kernel geometry gives the oracle's result (FP32 tolerance)."""
+    _require_gpu()
+    from paper_1903_03056_amd import CollisionPlan, tile_candidates
+    print(f"[case] tiles N={N}", flush=True)
+    rng = np.random.default_rng(N + 100)
+    masses = (1.0, 2.0)
+    f = I.draw_bimaxwellian_batch(rng, 1, 2, N, 6.0, masses, noise=1e-2).astype(np.float32).astype(np.float64)
+    ref = OS.collide(f[0], _oracle_problem(masses, 0.74, 6.0, N, M, nrho))
+    for tile in tile_candidates(N, "f32"):
+        print(f"[case] tile {tile}", flush=True)
+        plan = CollisionPlan(masses, N, 6.0, M, nrho, omega=0.74, precision="f32", tile=tile)
+        assert _rel(_run(plan, f)[0], ref) <= 1e-5, tile
+
+
+def _uneven_group():
+    from paper_1903_03056_amd import CollisionGroup, CollisionPlan
+    masses = (1.0, 2.0, 4.0)
+    shapes = [(24, 3), (32, 2), (48, 1)]
+    plans = [CollisionPlan(masses, N, 6.0, 6, 4, omega=0.74, precision="f32") for N, _ in shapes]
+    rng = np.random.default_rng(4)
+    fs = [I.draw_bimaxwellian_batch(rng, b, 3, N, 6.0, masses).astype(np.float32) for N, b in shapes]
+    return masses, shapes, plans, CollisionGroup(plans), fs
+
+
+def test_group_uneven_batch():
+    """N = 24, 32 and 48 nodes of 3 species in one group call: one node per class
+    against the oracle, every class equal bit for bit to its plan alone."""
+    _require_gpu()
+    print("[case] group uneven", flush=True)
+    masses, shapes, plans, group, fs = _uneven_group()
+    ft = [torch.tensor(f, device="cuda") for f in fs]
+    outs = group.collide(ft)
+    torch.cuda.synchronize()
+    for (N, b), plan, f, q, x in zip(shapes, plans, fs, outs, ft):
+        alone = plan.collide(x)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, q), N
+        ref = OS.collide(f[0].astype(np.float64), _oracle_problem(masses, 0.74, 6.0, N, 6, 4))
+        assert _rel(q[0].double().cpu().numpy(), ref) <= 1e-5, N
+
+
+def test_group_graph_replays():
+    """The captured graph replayed several times, with new inputs written eagerly
+    between replays; every replay equals the eager group call on the same inputs."""
+    _require_gpu()
+    print("[case] group graph", flush=True)
+    masses, shapes, plans, group, fs = _uneven_group()
+    ft = [torch.tensor(f, device="cuda") for f in fs]
+    graph, gout = group.capture(ft)
+    rng = np.random.default_rng(99)
+    for rep in range(3):
+        for x in ft:
+            x.mul_(float(rng.uniform(0.5, 1.5)))
+            x.add_(torch.rand_like(x) * 1e-3)
+        torch.cuda.synchronize()
+        graph.launch()
+        graph.stream.synchronize()
+        eager = group.collide(ft)
+        torch.cuda.synchronize()
+        for a, b in zip(gout, eager):
+            assert torch.equal(a, b), rep
+    graph.close()
+
+
+def test_autotuner_picks_a_candidate(tmp_path, monkeypatch):
+    _require_gpu()
+    print("[case] autotune", flush=True)
+    from paper_1903_03056_amd import CollisionPlan, tile_candidates, vhs_kernel
+    from paper_1903_03056_amd import autotune
+    monkeypatch.setenv("DGFS_TUNE_CACHE", str(tmp_path / "tiles.json"))
+    masses = (1.0, 2.0)
+    best = autotune.best_tile(masses, 32, 6.0, 12, 16, vhs_kernel(masses, 0.74), "f32", batch=8, reps=2)
+    assert best in tile_candidates(32, "f32")
+    assert (tmp_path / "tiles.json").exists()
+    plan = CollisionPlan(masses, 32, 6.0, 12, 16, omega=0.74, precision="f32", tile="auto")
+    assert plan.tile == best
+
+
+# ------------------------------------------------------ plain FP64 path
+@pytest.mark.parametrize("N,M,nrho", [(16, 12, 8), (24, 6, 6)])
+def test_plain_fp64_path_vs_oracle_and_fused(N, M, nrho):
+    """The plain per-point FP64 path (unfused, all directions per ordered pair) equals
+    the oracle to 1e-12 and the fused FP64 path to 1e-13."""
+    _require_gpu()
+    print(f"[case] plain fp64 N={N}", flush=True)
+    rng = np.random.default_rng(17)
+    masses = (1.0, 2.0)
+    f = I.draw_bimaxwellian_batch(rng, 2, 2, N, 6.0, masses, noise=1e-2)
+    plan = _plan(masses, N, 6.0, M, nrho, 0.74, "f64")
+    ft = torch.tensor(f, device="cuda")
+    Qp = plan.collide_plain(ft)
+    Qf = plan.collide(ft)
+    torch.cuda.synchronize()
+    qp, qf = Qp.cpu().numpy(), Qf.cpu().numpy()
+    prob = _oracle_problem(masses, 0.74, 6.0, N, M, nrho)
+    for b in range(2):
+        assert _rel(qp[b], OS.collide(f[b], prob)) <= 1e-12
+        assert _rel(qf[b], qp[b]) <= 1e-13
+
+
+def test_plain_path_rejects_fp32_plan():
+    _require_gpu()
+    from paper_1903_03056_amd._lib import DgfsError
+    plan = _plan((1.0, 2.0), 16, 5.0, 6, 8, 1.0, "f32")
+    with pytest.raises(DgfsError):
+        plan.collide_plain(torch.zeros((1, 2, 16, 16, 16), dtype=torch.float32, device="cuda"))
+
+
 # --------------------------------------------------------------- conservation
 @pytest.mark.parametrize("precision", ["f32", "f64"])
 def test_conserve_matches_oracle_projection(precision):
