@@ -143,6 +143,13 @@ dgfs_status dgfs_collide_plain(const dgfs_plan* plan, const double* f, double* Q
 dgfs_status dgfs_conserve(const dgfs_plan* plan, const void* Q_raw, double* Q_out, int64_t batch,
                           void* stream);
 
+/* One forward-Euler step of the spatially homogeneous relaxation df/dt = Q:
+ *     f <- f + dt * (Q_raw - A^T (A A^T)^{-1} A Q_raw)
+ * with the projection of dgfs_conserve, computed in FP64 and stored back into f in the
+ * plan precision.  f, Q_raw: device [batch][s][N^3], must not overlap. */
+dgfs_status dgfs_conserve_update(const dgfs_plan* plan, const void* Q_raw, void* f, double dt, int64_t batch,
+                                 void* stream);
+
 /* Host-side view of the precomputed quantities of ordered pair (i, j), for tests:
  *   info[0..5] = a, b, gamma, C_ij, R_ij, number of phase directions used;
  *   rho, w_rho: [n_rho] radial nodes and weights on [0, R_ij];

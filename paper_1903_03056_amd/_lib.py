@@ -17,7 +17,8 @@ DGFS_FP32, DGFS_FP64 = 0, 1
 
 EXPORTED = (
     "dgfs_check_problem", "dgfs_plan_create", "dgfs_plan_destroy", "dgfs_workspace_size",
-    "dgfs_collide", "dgfs_collide_timed", "dgfs_collide_pairs", "dgfs_collide_plain", "dgfs_conserve", "dgfs_pair_tables", "dgfs_design",
+    "dgfs_collide", "dgfs_collide_timed", "dgfs_collide_pairs", "dgfs_collide_plain", "dgfs_conserve",
+    "dgfs_conserve_update", "dgfs_pair_tables", "dgfs_design",
     "dgfs_status_string", "dgfs_last_error", "dgfs_tile_candidates", "dgfs_group_create", "dgfs_group_destroy",
     "dgfs_group_workspace_size", "dgfs_group_collide", "dgfs_group_capture", "dgfs_graph_launch",
     "dgfs_graph_destroy",
@@ -71,6 +72,7 @@ def load() -> ctypes.CDLL:
     lib.dgfs_collide_timed.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_size_t, c_void_p,
                                        POINTER(ctypes.c_float)]
     lib.dgfs_conserve.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p]
+    lib.dgfs_conserve_update.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_int64, c_void_p]
     lib.dgfs_pair_tables.argtypes = [POINTER(Problem), c_int32, c_int32, POINTER(c_double), POINTER(c_double),
                                      POINTER(c_double), POINTER(c_double)]
     lib.dgfs_design.argtypes = [c_int32, POINTER(c_double)]

@@ -1,5 +1,7 @@
 """Build the HIP shared library libdgfs.so in-tree for gfx950.
 
+Every source is compiled to an object in parallel (objects in _build/), then linked.
+
 Usage: python -m paper_1903_03056_amd.build [--verbose] [--resource-usage]
 """
 from __future__ import annotations
@@ -7,19 +9,22 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libdgfs.so")
+OBJ = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.cpp", "precompute.cpp", "kernels.hip", "plain.hip"]
+SOURCES = ["api.cpp", "precompute.cpp", "kernels.hip", "plain.hip",
+           "tiles_16.hip", "tiles_24.hip", "tiles_32.hip", "tiles_48.hip"]
 
 FLAGS = [
-    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wno-unused-command-line-argument",
+    "-Wno-unused-command-line-argument", "-Wno-unused-result",
 ]
 
 
@@ -30,19 +35,33 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False, resource_usage: bool = False) -> str:
-    cmd = [hipcc(), *FLAGS, "-I", os.path.join(ROOT, "include")]
+def _compile(src: str, resource_usage: bool):
+    obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+    cmd = [hipcc(), *FLAGS, "-I", os.path.join(ROOT, "include"), "-c", os.path.join(CSRC, src), "-o", obj]
     if resource_usage:
-        cmd += ["-Rpass-analysis=kernel-resource-usage"]
-    cmd += [os.path.join(CSRC, s) for s in SOURCES] + ["-o", LIB + ".tmp"]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+        cmd.append("-Rpass-analysis=kernel-resource-usage")
     res = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True)
+    return obj, cmd, res
+
+
+def build(verbose: bool = False, resource_usage: bool = False) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS") or os.cpu_count() or 1)))
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(lambda s: _compile(s, resource_usage), SOURCES))
+    for obj, cmd, res in results:
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError(f"hipcc failed on {obj}")
+        if resource_usage:
+            sys.stderr.write(res.stderr)
+    link = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *[r[0] for r in results], "-o", LIB + ".tmp"]
+    res = subprocess.run(link, cwd=ROOT, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed")
-    if verbose or resource_usage:
-        sys.stderr.write(res.stderr)
+        raise RuntimeError("link failed")
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

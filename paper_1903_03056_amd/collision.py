@@ -210,6 +210,16 @@ class CollisionPlan:
                                            c_void_p(st.cuda_stream)), "dgfs_collide_plain")
         return out
 
+    def relax_step(self, f, Q, dt: float, stream=None):
+        """f <- f + dt * conserve(Q) in place (one forward-Euler step), FP64 arithmetic."""
+        import torch
+        self._check_f(f)
+        self._check_f(Q)
+        st = stream if stream is not None else torch.cuda.current_stream(f.device)
+        check(self._lib.dgfs_conserve_update(self._plan, c_void_p(Q.data_ptr()), c_void_p(f.data_ptr()), float(dt),
+                                             f.shape[0], c_void_p(st.cuda_stream)), "dgfs_conserve_update")
+        return f
+
     def conserve(self, Q, out=None, stream=None):
         """FP64 conservation projection of a raw collision result (same layout as f)."""
         import torch

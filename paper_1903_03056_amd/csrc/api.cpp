@@ -563,7 +563,20 @@ dgfs_status dgfs_conserve(const dgfs_plan* plan, const void* Q_raw, double* Q_ou
     if (!Q_raw || !Q_out) return fail(DGFS_EINVAL, "Q_raw and Q_out are required");
     if (plan->precision != DGFS_FP64 && static_cast<const void*>(Q_out) == Q_raw)
         return fail(DGFS_EINVAL, "Q_out may alias Q_raw only for FP64 plans");
-    hipError_t e = dgfs::launch_conserve(*plan, Q_raw, Q_out, batch, static_cast<hipStream_t>(stream));
+    hipError_t e = dgfs::launch_conserve(*plan, Q_raw, Q_out, nullptr, 0.0, batch, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(DGFS_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return DGFS_OK;
+}
+
+dgfs_status dgfs_conserve_update(const dgfs_plan* plan, const void* Q_raw, void* f, double dt, int64_t batch,
+                                 void* stream) {
+    if (!plan) return fail(DGFS_EINVAL, "plan is NULL");
+    if (batch < 0) return fail(DGFS_EINVAL, "batch must be >= 0");
+    if (batch == 0) return DGFS_OK;
+    if (!Q_raw || !f) return fail(DGFS_EINVAL, "Q_raw and f are required");
+    if (Q_raw == static_cast<const void*>(f)) return fail(DGFS_EINVAL, "Q_raw and f must not overlap");
+    if (!std::isfinite(dt)) return fail(DGFS_EINVAL, "dt must be finite");
+    hipError_t e = dgfs::launch_conserve(*plan, Q_raw, nullptr, f, dt, batch, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail(DGFS_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
     return DGFS_OK;
 }

@@ -86,7 +86,8 @@ namespace dgfs {
 // ev: NULL, or 6 events recorded at the stage boundaries of the slice.
 hipError_t launch_collide(const dgfs_plan& p, const void* f, void* Q, int64_t nb, void* ws,
                           bool pairs, hipStream_t stream, hipEvent_t* ev);
-hipError_t launch_conserve(const dgfs_plan& p, const void* Q, double* out, int64_t nb,
+// out != NULL: out = projection of Q (FP64); fstate != NULL: fstate += dt * projection.
+hipError_t launch_conserve(const dgfs_plan& p, const void* Q, double* out, void* fstate, double dt, int64_t nb,
                            hipStream_t stream);
 // Plain per-point FP64 path (plain.hip).
 size_t plain_ws_bytes(const dgfs_plan& p);

@@ -350,3 +350,48 @@ def test_conserve_matches_oracle_projection(precision):
         ref = OM.conserve(raw[b], masses, (6.0, 6.0))
         assert np.abs(got[b] - ref).max() <= 1e-12 * np.abs(ref).max()
         assert np.all(OM.conservation_residual(got[b], masses, (6.0, 6.0)) <= 1e-12)
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_conserve_update_is_euler_step_of_projection(precision):
+    """dgfs_conserve_update: f <- f + dt * projection(Q) in FP64 arithmetic, stored in the
+    plan's precision, against the oracle's projection of the same raw result (within one
+    unit in the last place of the stored type, plus dt times the projection's own 1e-12
+    relative tolerance)."""
+    _require_gpu()
+    print(f"[case] conserve_update {precision}", flush=True)
+    rng = np.random.default_rng(17)
+    masses = (1.0, 2.0, 4.0)
+    f = I.draw_bimaxwellian_batch(rng, 3, 3, 16, 6.0, masses, noise=1e-2)
+    plan = _plan(masses, 16, 6.0, 12, 8, 0.74, precision)
+    dt_t = torch.float64 if precision == "f64" else torch.float32
+    np_t = np.float64 if precision == "f64" else np.float32
+    ft = torch.tensor(f, dtype=dt_t, device="cuda")
+    Qr = plan.collide(ft)
+    f0 = ft.double().cpu().numpy()
+    raw = Qr.double().cpu().numpy()
+    dt = 0.01
+    plan.relax_step(ft, Qr, dt)
+    torch.cuda.synchronize()
+    got = ft.cpu().numpy()
+    for b in range(3):
+        proj = OM.conserve(raw[b], masses, (6.0,) * 3)
+        ref = (f0[b] + dt * proj).astype(np_t)
+        tol = np.spacing(np.abs(ref)).astype(np.float64) + dt * 1e-12 * np.abs(proj).max()
+        assert np.all(np.abs(got[b].astype(np.float64) - ref.astype(np.float64)) <= tol)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_large_mass_ratio(precision, tol):
+    """Masses (1, 4, 20) (mass ratio 20: a, b = 1/21, 20/21 for the light-heavy pair),
+    N = 24, M = 12, N_rho = 12, L = 6, omega = 0.74."""
+    _require_gpu()
+    print(f"[case] mass ratio 20 {precision}", flush=True)
+    rng = np.random.default_rng(23)
+    masses = (1.0, 4.0, 20.0)
+    f = I.draw_bimaxwellian_batch(rng, 2, 3, 24, 6.0, masses)
+    Q = _run(_plan(masses, 24, 6.0, 12, 12, 0.74, precision), f)
+    prob = _oracle_problem(masses, 0.74, 6.0, 24, 12, 12)
+    for b in range(2):
+        ref = OS.collide(f[b].astype(np.float32).astype(np.float64) if precision == "f32" else f[b], prob)
+        assert _rel(Q[b], ref) <= tol
