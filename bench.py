@@ -12,7 +12,6 @@ Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -51,16 +50,16 @@ def gain_flops_per_node(N, M, n_rho, s, antipodal=True):
     return dirs * n_rho * (2 * (fft + 6 * n3) + 10 * n3) + ncls * n_rho * fft
 
 
-def load_traffic(kernel_src):
+def load_traffic():
     """HBM bytes per launch of the gain kernel from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source (else None)."""
+    from paper_1903_03056_amd.rocprof_summary import gain_source_digest
     path = os.path.join(ROOT, "profiles", "gain_kernel_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    digest = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    if rec.get("kernel_source_sha256") != digest:
+    if rec.get("kernel_source_sha256") != gain_source_digest():
         return None
     return rec.get("bytes_per_launch")
 
@@ -91,6 +90,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="leave out the plain per-point FP64 comparison leg (not part of the timed step)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain device copy of 2 x 256 MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -161,8 +162,7 @@ def main():
     gain_ms = stage_avg[1]
     flop_node = gain_flops_per_node(w["N"], w["M"], w["n_rho"], s)
     achieved = flop_node * w["batch"] / (gain_ms / 1e3) / 1e12
-    kernel_src = os.path.join(ROOT, "paper_1903_03056_amd", "csrc", "kernels.hip")
-    traffic = load_traffic(kernel_src)
+    traffic = load_traffic()
     cons_avg = float(np.mean(cons_ms))
     cons_bytes = w["batch"] * s * w["N"] ** 3 * (4 + 8)
     cons_gbps = cons_bytes / (cons_avg / 1e3) / 1e9
@@ -199,17 +199,18 @@ def main():
         "precompute_s": round(precompute_s, 3),
     }
     # the plain per-point FP64 GPU path on the first nodes of the same workload
-    plain_nodes = 2
-    plan64 = CollisionPlan(w["masses"], w["N"], w["L"], w["M"], w["n_rho"], omega=w["omega"], precision="f64")
-    f64d = torch.tensor(f32[:plain_nodes].astype(np.float64), device=dev)
-    Qp = plan64.collide_plain(f64d[:1])          # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    Qp = plan64.collide_plain(f64d)
-    torch.cuda.synchronize()
-    plain_s = time.perf_counter() - t0
-    out["plain_fp64_path"] = {"value": round(plain_nodes * s * s / plain_s, 2), "unit": "evals/s",
-                              "sample": f"first {plain_nodes} nodes, one node per pass, unfused FP64 kernels"}
+    plain_nodes = 0 if args.no_plain else 2
+    if plain_nodes:
+        plan64 = CollisionPlan(w["masses"], w["N"], w["L"], w["M"], w["n_rho"], omega=w["omega"], precision="f64")
+        f64d = torch.tensor(f32[:plain_nodes].astype(np.float64), device=dev)
+        Qp = plan64.collide_plain(f64d[:1])          # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Qp = plan64.collide_plain(f64d)
+        torch.cuda.synchronize()
+        plain_s = time.perf_counter() - t0
+        out["plain_fp64_path"] = {"value": round(plain_nodes * s * s / plain_s, 2), "unit": "evals/s",
+                                  "sample": f"first {plain_nodes} nodes, one node per pass, unfused FP64 kernels"}
 
     def rel_err(a, ref):
         num = np.abs(a - ref).reshape(s, -1).max(1)
@@ -219,10 +220,11 @@ def main():
         base, outs = cpu_baseline(f32.astype(np.float64))
         out["cpu_baseline"] = base
         Qh = Q.double().cpu().numpy()
-        Qph = Qp.cpu().numpy()
         out["max_rel_linf_vs_oracle"] = max(rel_err(Qh[b], ref) for b, ref in enumerate(outs))
-        out["plain_fp64_path"]["max_rel_linf_vs_oracle"] = max(
-            rel_err(Qph[b], outs[b]) for b in range(min(plain_nodes, len(outs))))
+        if plain_nodes:
+            Qph = Qp.cpu().numpy()
+            out["plain_fp64_path"]["max_rel_linf_vs_oracle"] = max(
+                rel_err(Qph[b], outs[b]) for b in range(min(plain_nodes, len(outs))))
     print(json.dumps(out), flush=True)
 
 

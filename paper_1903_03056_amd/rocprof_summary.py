@@ -23,6 +23,18 @@ COPY_BYTES = 256 * 1024 * 1024
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
+GAIN_SOURCES = ("gain.hpp", "fft.hpp", "passes.hpp", "tiles_32.hip")
+
+
+def gain_source_digest() -> str:
+    """SHA-256 over the sources the N=32 gain kernel is compiled from."""
+    h = hashlib.sha256()
+    for name in GAIN_SOURCES:
+        with open(os.path.join(ROOT, "paper_1903_03056_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def _one(pattern):
     hits = glob.glob(pattern)
     if not hits:
@@ -40,7 +52,7 @@ def _counters(d, counter):
 
 
 def short(name):
-    name = name.replace("dgfs::", "")
+    name = name.replace("dgfs::", "").replace("(anonymous namespace)::", "")
     return name.split("(")[0]
 
 
@@ -72,13 +84,12 @@ def main(trace_dir, fetch_dir, write_dir, prefix, command):
     gain = [(fv, wv) for (k, fv), (k2, wv) in zip(fetch, write) if "gain_kernel" in k and k == k2]
     if gain:
         fv, wv = gain[-1]
-        src = os.path.join(ROOT, "paper_1903_03056_amd", "csrc", "kernels.hip")
         rec = {"kernel": "gain_kernel<float, 32, ...>",
                "workload": "256-node N=32 slab (bench.py)",
                "bytes_per_launch": fv * ff + wv * fw,
                "read_bytes": fv * ff, "write_bytes": wv * fw,
                "fetch_factor": ff, "write_factor": fw,
-               "kernel_source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+               "kernel_source_sha256": gain_source_digest(),
                "commands": command}
         with open(os.path.join(ROOT, "profiles", "gain_kernel_traffic.json"), "w") as fh:
             json.dump(rec, fh, indent=1)
@@ -90,8 +101,8 @@ if __name__ == "__main__":
         "trace": "rocprofv3 --kernel-trace --stats -d DIR -o trace --output-format csv -- "
                  "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline",
         "fetch": "rocprofv3 --pmc FETCH_SIZE -d DIR -o fetch --output-format csv -- "
-                 "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --copy-probe",
+                 "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-plain --copy-probe",
         "write": "rocprofv3 --pmc WRITE_SIZE -d DIR -o write --output-format csv -- "
-                 "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --copy-probe",
+                 "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-plain --copy-probe",
     }
     main(t, f, w, p, cmds)
