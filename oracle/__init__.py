@@ -14,5 +14,8 @@ Galerkin fast spectral method for the multi-species Boltzmann equation"):
                   O(N^6) spectral sum, the fast sum, and the exact-sphere variant.
 * ``moments``     moments, the Maxwellian, the FP64 conservation projection.
 * ``bkw``         the Krook-Wu exact solution and its time derivative (Sec. 6.1).
+* ``grids``       species-specific velocity grids: trigonometric interpolation between
+                  grids and the pairwise evaluation on the wider grid (the remedy the
+                  remark after eq. (domain) in Sec. 4 names and leaves for later).
 """
-from . import params, quadrature, spectral, moments, bkw  # noqa: F401
+from . import params, quadrature, spectral, moments, bkw, grids  # noqa: F401
