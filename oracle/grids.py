@@ -14,9 +14,12 @@ remedy, which the paper leaves for later.  The reading implemented here:
   that grid (all points of the narrower grid i lie inside the wider box);
 * Q^i = sum_j Q^{ij}; the conservation projection then runs on the species' own grids.
 
-The interpolant of f on grid L is p(v) = Re sum_k f_hat_k e^{i pi k.v / L} with f_hat the
-coefficients of Sec. 4 (modes k in [-N/2, N/2-1]); for real data, the real part is the
-series with the Nyquist mode split evenly between +N/2 and -N/2.
+The interpolant of f on grid L is the real trigonometric interpolant
+p(v) = sum_k f_hat_k c_{k_x}(v_x) c_{k_y}(v_y) c_{k_z}(v_z), with f_hat the coefficients of
+Sec. 4 (modes k in [-N/2, N/2-1]), c_k(x) = e^{i pi k x / L} for |k| < N/2 and
+c_{-N/2}(x) = cos(pi N x / (2L)): the Nyquist mode split evenly between +N/2 and -N/2 in
+each dimension.  It agrees with the series at the grid points, is real for real data and
+is a product of one-dimensional maps.
 """
 from __future__ import annotations
 
@@ -30,11 +33,13 @@ def grid_points(N: int, L: float) -> np.ndarray:
 
 
 def _evaluation_matrix(N: int, L_from: float, L_to: float) -> np.ndarray:
-    """E[n, j] = e^{i pi k_j v_n / L_from} at the target points v_n of the grid L_to, with
-    k_j the signed mode of DFT index j; rows of points outside the source box are zero."""
+    """E[n, j] = c_{k_j}(v_n) at the target points v_n of the grid L_to, with k_j the signed
+    mode of DFT index j (the Nyquist column a cosine); rows of points outside the source
+    box are zero."""
     v = grid_points(N, L_to)
     k = S.signed_modes(N)
     E = np.exp(1j * np.pi * np.outer(v, k) / L_from)
+    E[:, N // 2] = np.cos(np.pi * (N // 2) * v / L_from)
     inside = (v >= -L_from) & (v < L_from)
     return E * inside[:, None]
 

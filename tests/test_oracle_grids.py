@@ -68,6 +68,20 @@ def test_trigonometric_polynomials_are_reproduced(N, L_from, L_to):
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(f).max()
 
 
+def test_nyquist_in_two_dimensions_stays_a_product_of_cosines():
+    """cos(pi N x / 2L) cos(pi N y / 2L) is reproduced exactly: the Nyquist mode is split
+    evenly in each dimension (the literal -N/2 series would give cos(a + b) instead)."""
+    N, L_from, L_to = 8, 1.0, 1.37
+    vs = G.grid_points(N, L_from)
+    c = np.cos(np.pi * (N // 2) * vs / L_from)
+    f = c[:, None, None] * c[None, :, None] * np.ones(N)[None, None, :]
+    vt = G.grid_points(N, L_to)
+    inside = (vt >= -L_from) & (vt < L_from)
+    ct = np.where(inside, np.cos(np.pi * (N // 2) * vt / L_from), 0.0)
+    ref = ct[:, None, None] * ct[None, :, None] * inside[None, None, :]
+    assert np.abs(G.interpolate(f, L_from, L_to) - ref).max() <= 1e-13
+
+
 def test_equal_boxes_reduce_to_the_single_grid_operator():
     masses = (1.0, 2.0)
     prob = S.vhs_problem(masses, 0.74, 5.0, 8, 6, 4)
