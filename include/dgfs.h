@@ -18,7 +18,8 @@
  * Conventions (shared by every entry point):
  *   - Distribution functions and results are laid out [batch][s][N][N][N], the last
  *     (z) index fastest, real, in the plan's precision (float or double).
- *   - Species i is sampled at v_n = -L + n 2L/N, n = 0..N-1, per dimension.
+ *   - Species i is sampled at v_n = -L + n 2L/N, n = 0..N-1, per dimension (with
+ *     species-specific grids, L is that species' own half-width L_i).
  *   - Mode k of the truncated series runs over [-N/2, N/2-1]^3 (Sec. 4); the DFT
  *     index N/2 stands for the mode -N/2.  The sum over l + m = k in eq. (sum) is
  *     taken modulo N (circular), which is what its FFT evaluation computes.
@@ -69,11 +70,22 @@ typedef struct {
 typedef struct {
     int32_t s;                       /* number of species, 1..8 */
     const double* mass;              /* [s] nondimensional masses, > 0 */
-    double L;                        /* half-width of the velocity box [-L, L]^3, > 0 */
-    const double* L_species;         /* NULL, or [s] per-species half-widths (species-specific
-                                        grids; only the common-grid case is implemented:
-                                        a non-NULL array with unequal entries returns
-                                        DGFS_EUNSUPPORTED) */
+    double L;                        /* half-width of the velocity box [-L, L]^3, > 0;
+                                        ignored when L_species is given */
+    const double* L_species;         /* NULL (every species on [-L, L]^3), or [s] half-widths
+                                        L_i > 0 of species-specific grids.  Species i is then
+                                        sampled at v_n = -L_i + n 2L_i/N, and the ordered pair
+                                        (i, j) is evaluated by the method of Sec. 4 on the box
+                                        of half-width L_ij = max(L_i, L_j) (R_ij and all tables
+                                        for that box): a narrower species is carried onto it
+                                        by its real trigonometric interpolant (Nyquist mode
+                                        split evenly per dimension; zero outside its own box
+                                        [-L_i, L_i)), and Q^{ij} is carried back to grid i by
+                                        the interpolant of the L_ij grid.  The remark after
+                                        eq. (domain) in Sec. 4 names such grids for large mass
+                                        ratios; the carrying rule is this library's choice.
+                                        The conservation correction then uses each species'
+                                        own grid.  dgfs_collide_plain needs one common grid. */
     int32_t N;                       /* modes per dimension: 16, 24, 32 or 48 */
     int32_t M;                       /* spherical design size: 6, 12 or 24 */
     int32_t n_rho;                   /* radial Gauss-Legendre points, 1..128 */
@@ -136,7 +148,8 @@ dgfs_status dgfs_collide_plain(const dgfs_plan* plan, const double* f, double* Q
 
 /* FP64 conservation correction (least-squares projection onto the collision
  * invariants of Sec. 2, eq. consv): with A the (s+4) x (s N^3) matrix of species
- * numbers, total momentum and total energy (rectangle rule, weight h^3 and m_i),
+ * numbers, total momentum and total energy (rectangle rule, weight h_i^3 and m_i on
+ * species i's grid),
  *     Q_out = Q_raw - A^T (A A^T)^{-1} A Q_raw      per node, in FP64.
  * Q_raw: device [batch][s][N^3] in the plan precision; Q_out: device double array of
  * the same shape (may alias Q_raw only when the plan precision is FP64). */
@@ -192,6 +205,13 @@ void dgfs_graph_destroy(void* graph);
 
 /* Host-side copy of the M-point design used by the plan, [M][3]. */
 dgfs_status dgfs_design(int32_t M, double* sigma);
+
+/* Host-side copy of the one-dimensional map between species grids used with
+ * L_species, for tests: T[r*N + n] weights sample n of the grid of half-width L_from to
+ * give the real trigonometric interpolant at point r of the grid of half-width L_to
+ * (zero rows for points outside [-L_from, L_from)); the three-dimensional map applies T
+ * along each axis.  T: [N][N] host doubles.  No device is touched. */
+dgfs_status dgfs_interpolation_matrix(int32_t N, double L_from, double L_to, double* T);
 
 const char* dgfs_status_string(dgfs_status status);
 const char* dgfs_last_error(void);

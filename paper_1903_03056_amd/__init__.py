@@ -11,6 +11,7 @@ from .collision import (  # noqa: F401
     tile_candidates,
     check_problem,
     design,
+    interpolation_matrix,
     pair_tables,
     vhs_kernel,
     vhs_prefactor,

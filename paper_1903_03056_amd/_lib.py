@@ -18,7 +18,7 @@ DGFS_FP32, DGFS_FP64 = 0, 1
 EXPORTED = (
     "dgfs_check_problem", "dgfs_plan_create", "dgfs_plan_destroy", "dgfs_workspace_size",
     "dgfs_collide", "dgfs_collide_timed", "dgfs_collide_pairs", "dgfs_collide_plain", "dgfs_conserve",
-    "dgfs_conserve_update", "dgfs_pair_tables", "dgfs_design",
+    "dgfs_conserve_update", "dgfs_pair_tables", "dgfs_design", "dgfs_interpolation_matrix",
     "dgfs_status_string", "dgfs_last_error", "dgfs_tile_candidates", "dgfs_group_create", "dgfs_group_destroy",
     "dgfs_group_workspace_size", "dgfs_group_collide", "dgfs_group_capture", "dgfs_graph_launch",
     "dgfs_graph_destroy",
@@ -76,6 +76,7 @@ def load() -> ctypes.CDLL:
     lib.dgfs_pair_tables.argtypes = [POINTER(Problem), c_int32, c_int32, POINTER(c_double), POINTER(c_double),
                                      POINTER(c_double), POINTER(c_double)]
     lib.dgfs_design.argtypes = [c_int32, POINTER(c_double)]
+    lib.dgfs_interpolation_matrix.argtypes = [c_int32, c_double, c_double, POINTER(c_double)]
     lib.dgfs_tile_candidates.argtypes = [c_int32, c_int32, POINTER(c_int32), c_int32, POINTER(c_int32)]
     lib.dgfs_group_create.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_void_p)]
     lib.dgfs_group_destroy.argtypes = [c_void_p]

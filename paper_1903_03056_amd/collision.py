@@ -76,10 +76,18 @@ def design(M: int) -> np.ndarray:
     return np.array(out[:]).reshape(M, 3)
 
 
-def pair_tables(masses, L, N, M, n_rho, kernel, i, j, precision="f32") -> dict:
+def interpolation_matrix(N: int, L_from: float, L_to: float) -> np.ndarray:
+    """The library's one-dimensional map between species grids, [N][N]."""
+    lib = load()
+    out = (c_double * (N * N))()
+    check(lib.dgfs_interpolation_matrix(N, float(L_from), float(L_to), out), "dgfs_interpolation_matrix")
+    return np.array(out[:]).reshape(N, N)
+
+
+def pair_tables(masses, L, N, M, n_rho, kernel, i, j, precision="f32", L_species=None) -> dict:
     """Host-side precomputed quantities of ordered pair (i, j)."""
     lib = load()
-    h = _ProblemHolder(masses, L, N, M, n_rho, kernel, precision)
+    h = _ProblemHolder(masses, L, N, M, n_rho, kernel, precision, L_species)
     info = (c_double * 6)()
     rho = (c_double * n_rho)()
     wrho = (c_double * n_rho)()
@@ -96,7 +104,7 @@ class CollisionPlan:
     kernel[i][j] = (omega, alpha, prefactor); default: VHS with ``omega`` and the
     prefactor of eqs. (Kn)/(NVSS) with Kn0 = ``kn0``."""
 
-    def __init__(self, masses, N: int, L: float, M: int, n_rho: int, omega: float | None = None,
+    def __init__(self, masses, N: int, L, M: int, n_rho: int, omega: float | None = None,
                  kernel=None, precision="f32", kn0: float = 1.0, tile=None):
         import torch  # noqa: F401  (initialises the HIP runtime the library shares)
 
@@ -105,14 +113,18 @@ class CollisionPlan:
                 raise ValueError("give omega or kernel")
             kernel = vhs_kernel(masses, omega, 1.0, kn0)
         self.masses = tuple(float(m) for m in masses)
-        self.s, self.N, self.L, self.M, self.n_rho = len(masses), N, float(L), M, n_rho
+        # L: one half-width for every species, or one per species (species-specific grids)
+        Ls = np.broadcast_to(np.asarray(L, dtype=np.float64), (len(masses),))
+        self.L_species = tuple(float(x) for x in Ls)
+        self.s, self.N, self.L, self.M, self.n_rho = len(masses), N, max(self.L_species), M, n_rho
         self.kernel = kernel
         self.precision = _precision_code(precision)
         if tile == "auto":
             from .autotune import best_tile
-            tile = best_tile(self.masses, N, L, M, n_rho, kernel, precision)
+            tile = best_tile(self.masses, N, self.L, M, n_rho, kernel, precision)
         self.tile = tuple(tile) if tile else None
-        self._holder = _ProblemHolder(self.masses, L, N, M, n_rho, kernel, precision, tile=self.tile)
+        Lsp = self.L_species if len(set(self.L_species)) > 1 else None
+        self._holder = _ProblemHolder(self.masses, self.L, N, M, n_rho, kernel, precision, Lsp, tile=self.tile)
         self._lib = load()
         handle = c_void_p()
         check(self._lib.dgfs_plan_create(ctypes.byref(self._holder.problem), ctypes.byref(handle)),

@@ -34,7 +34,13 @@ dgfs_status check(const dgfs_problem* p) {
     if (!p->mass || !p->kernel) return fail(DGFS_EINVAL, "mass and kernel arrays are required");
     for (int i = 0; i < p->s; ++i)
         if (!(p->mass[i] > 0.0) || !std::isfinite(p->mass[i])) return fail(DGFS_EINVAL, "masses must be positive");
-    if (!(p->L > 0.0) || !std::isfinite(p->L)) return fail(DGFS_EINVAL, "L must be positive");
+    if (p->L_species) {
+        for (int i = 0; i < p->s; ++i)
+            if (!(p->L_species[i] > 0.0) || !std::isfinite(p->L_species[i]))
+                return fail(DGFS_EINVAL, "L_species must be positive");
+    } else if (!(p->L > 0.0) || !std::isfinite(p->L)) {
+        return fail(DGFS_EINVAL, "L must be positive");
+    }
     if (p->N < 4 || p->N % 2 != 0) return fail(DGFS_EINVAL, "N must be even and >= 4");
     if (p->M != 6 && p->M != 12 && p->M != 24) return fail(DGFS_EINVAL, "no spherical design for this M (6, 12, 24)");
     if (p->n_rho < 1 || p->n_rho > 128) return fail(DGFS_EINVAL, "n_rho must be in [1, 128]");
@@ -49,12 +55,6 @@ dgfs_status check(const dgfs_problem* p) {
                 return fail(DGFS_EINVAL, "prefactor must be positive");
             if (k.omega != t.omega || k.alpha != t.alpha || k.prefactor != t.prefactor)
                 return fail(DGFS_EINVAL, "kernel must be symmetric in (i, j)");
-        }
-    if (p->L_species)
-        for (int i = 0; i < p->s; ++i) {
-            if (!(p->L_species[i] > 0.0)) return fail(DGFS_EINVAL, "L_species must be positive");
-            if (p->L_species[i] != p->L)
-                return fail(DGFS_EUNSUPPORTED, "species-specific grids are not implemented");
         }
     for (int i = 0; i < p->s * p->s; ++i)
         if (p->kernel[i].alpha != 1.0) return fail(DGFS_EUNSUPPORTED, "VSS kernels (alpha > 1) are not implemented");
@@ -72,6 +72,12 @@ dgfs_status check(const dgfs_problem* p) {
     return DGFS_OK;
 }
 
+// Half-width of the box the ordered pair (i, j) is evaluated on: the common L, or with
+// species-specific grids the wider of the two species' boxes.
+double pair_box(const dgfs_problem* p, int i, int j) {
+    return p->L_species ? std::max(p->L_species[i], p->L_species[j]) : p->L;
+}
+
 dgfs::PairParams pair_params(const dgfs_problem* p, int i, int j) {
     dgfs::PairParams pp;
     const double mi = p->mass[i], mj = p->mass[j];
@@ -79,7 +85,7 @@ dgfs::PairParams pair_params(const dgfs_problem* p, int i, int j) {
     pp.b = mi / (mi + mj);
     pp.gamma = 2.0 * (1.0 - p->kernel[i * p->s + j].omega);
     pp.C = p->kernel[i * p->s + j].prefactor;
-    pp.R = dgfs::pre::truncation_radius(p->L, mi, mj);
+    pp.R = dgfs::pre::truncation_radius(pair_box(p, i, j), mi, mj);
     dgfs::pre::gauss_legendre(p->n_rho, pp.R, pp.rho, pp.wrho);
     return pp;
 }
@@ -115,6 +121,8 @@ bool invert(std::vector<double> A, int n, std::vector<double>& inv) {
     return true;
 }
 
+inline size_t detail_align(size_t x) { return (x + 255) & ~size_t(255); }
+
 template <typename T>
 void push_real(std::vector<char>& blob, size_t& off, const std::vector<double>& v) {
     off = (blob.size() + 255) & ~size_t(255);
@@ -141,6 +149,45 @@ void push_int(std::vector<char>& blob, size_t& off, const std::vector<int>& v) {
 }
 
 void push_double(std::vector<char>& blob, size_t& off, const std::vector<double>& v) { push_real<double>(blob, off, v); }
+
+// FP64 conservation data: the inverse Gram matrix (A A^T)^{-1} of the s+4 invariant
+// rows, then the masses and the grid half-widths.  Rows of A: h_i^3 on species i (s
+// rows), m_i h_i^3 v_d (3 rows), m_i h_i^3 |v|^2 (1 row), with h_i = 2 L_i / N and
+// v = -L_i + n h_i on species i's grid; A A^T in closed form from the power sums of the
+// one-dimensional grid of each species.
+std::vector<double> conserve_pack(const std::vector<double>& mass, const std::vector<double>& Ls, int N) {
+    const int s = int(mass.size()), nr = s + 4;
+    const double Nd = N;
+    std::vector<double> Gm(nr * nr, 0.0);
+    for (int i = 0; i < s; ++i) {
+        const double L = Ls[i], h = 2.0 * L / N, h6 = std::pow(h, 6), m = mass[i];
+        double S1 = 0, S2 = 0, S3 = 0, S4 = 0;
+        for (int n = 0; n < N; ++n) {
+            const double v = -L + n * h;
+            S1 += v;
+            S2 += v * v;
+            S3 += v * v * v;
+            S4 += v * v * v * v;
+        }
+        Gm[i * nr + i] = h6 * Nd * Nd * Nd;
+        for (int d = 0; d < 3; ++d) Gm[i * nr + s + d] = Gm[(s + d) * nr + i] = m * h6 * Nd * Nd * S1;
+        Gm[i * nr + s + 3] = Gm[(s + 3) * nr + i] = m * h6 * 3.0 * Nd * Nd * S2;
+        const double m2h6 = m * m * h6;
+        for (int d = 0; d < 3; ++d)
+            for (int e = 0; e < 3; ++e) Gm[(s + d) * nr + s + e] += m2h6 * (d == e ? Nd * Nd * S2 : Nd * S1 * S1);
+        for (int d = 0; d < 3; ++d) {
+            const double x = m2h6 * (Nd * Nd * S3 + 2.0 * Nd * S1 * S2);
+            Gm[(s + d) * nr + s + 3] += x;
+            Gm[(s + 3) * nr + s + d] += x;
+        }
+        Gm[(s + 3) * nr + s + 3] += m2h6 * (3.0 * Nd * Nd * S4 + 6.0 * Nd * S2 * S2);
+    }
+    std::vector<double> inv;
+    invert(Gm, nr, inv);
+    inv.insert(inv.end(), mass.begin(), mass.end());
+    inv.insert(inv.end(), Ls.begin(), Ls.end());
+    return inv;
+}
 
 // Build every host table and lay it out in one byte blob for the device.
 template <typename T>
@@ -222,6 +269,7 @@ void build_tables(dgfs_plan& P, std::vector<char>& blob) {
         if (c.i != c.j && P.antipodal) targets.push_back(c.j);
         for (int tg : targets) {
             const int other = tg == c.i ? c.j : c.i;
+            if (!P.mask[tg * s + other]) continue;
             const dgfs::PairParams& pp = P.pair[tg * s + other];
             for (int q = 0; q < nrho; ++q)
                 for (int k2 = 0; k2 < K2; ++k2)
@@ -269,7 +317,8 @@ void build_tables(dgfs_plan& P, std::vector<char>& blob) {
             const int g0 = int(S.gterms.size() / 2), l0 = int(S.lterms.size() / 2);
             for (size_t k = 0; k < P.classes.size(); ++k)
                 if (ftab[k][i] >= 0) S.gterms.insert(S.gterms.end(), {int(k), ftab[k][i]});
-            for (int j = 0; j < s; ++j) S.lterms.insert(S.lterms.end(), {j, i * s + j});
+            for (int j = 0; j < s; ++j)
+                if (P.mask[i * s + j]) S.lterms.insert(S.lterms.end(), {j, i * s + j});
             S.slots.insert(S.slots.end(), {i, g0, int(S.gterms.size() / 2) - g0, l0, int(S.lterms.size() / 2) - l0});
         }
         push_int(blob, S.off_slots, S.slots);
@@ -282,8 +331,12 @@ void build_tables(dgfs_plan& P, std::vector<char>& blob) {
         S.nslots = s * s;
         for (int i = 0; i < s; ++i)
             for (int j = 0; j < s; ++j) {
-                const int k = cls_of(i, j);
                 const int g0 = int(S.gterms.size() / 2), l0 = int(S.lterms.size() / 2);
+                if (!P.mask[i * s + j]) {  // evaluated elsewhere: an empty slot (zero output)
+                    S.slots.insert(S.slots.end(), {i, g0, 0, l0, 0});
+                    continue;
+                }
+                const int k = cls_of(i, j);
                 S.gterms.insert(S.gterms.end(), {k, ftab[k][i]});
                 S.lterms.insert(S.lterms.end(), {j, i * s + j});
                 S.slots.insert(S.slots.end(), {i, g0, 1, l0, 1});
@@ -323,43 +376,247 @@ void build_tables(dgfs_plan& P, std::vector<char>& blob) {
         push_double(blob, P.off_plain_F, pF);
     }
 
-    // ---------------- conservation: inverse Gram matrix of the s+4 invariants, masses
-    {
-        const int nr = s + 4;
-        const double h = 2.0 * L / N, h6 = std::pow(h, 6);
-        double S1 = 0, S2 = 0, S3 = 0, S4 = 0;
-        for (int n = 0; n < N; ++n) {
-            const double v = -L + n * h;
-            S1 += v;
-            S2 += v * v;
-            S3 += v * v * v;
-            S4 += v * v * v * v;
-        }
-        const double Nd = N;
-        double msum2 = 0;
-        for (int i = 0; i < s; ++i) msum2 += P.mass[i] * P.mass[i];
-        std::vector<double> Gm(nr * nr, 0.0);
-        for (int i = 0; i < s; ++i) {
-            Gm[i * nr + i] = h6 * Nd * Nd * Nd;
-            for (int d = 0; d < 3; ++d) Gm[i * nr + s + d] = Gm[(s + d) * nr + i] = P.mass[i] * h6 * Nd * Nd * S1;
-            Gm[i * nr + s + 3] = Gm[(s + 3) * nr + i] = P.mass[i] * h6 * 3.0 * Nd * Nd * S2;
-        }
-        for (int d = 0; d < 3; ++d)
-            for (int e = 0; e < 3; ++e) Gm[(s + d) * nr + s + e] = msum2 * h6 * (d == e ? Nd * Nd * S2 : Nd * S1 * S1);
-        for (int d = 0; d < 3; ++d)
-            Gm[(s + d) * nr + s + 3] = Gm[(s + 3) * nr + s + d] = msum2 * h6 * (Nd * Nd * S3 + 2.0 * Nd * S1 * S2);
-        Gm[(s + 3) * nr + s + 3] = msum2 * h6 * (3.0 * Nd * Nd * S4 + 6.0 * Nd * S2 * S2);
-        std::vector<double> inv;
-        invert(Gm, nr, inv);
-        std::vector<double> pack = inv;
-        pack.insert(pack.end(), P.mass.begin(), P.mass.end());
-        push_double(blob, P.off_minv, pack);
+    push_double(blob, P.off_minv, conserve_pack(P.mass, P.Ls, N));
+}
+
+}  // namespace
+
+namespace {
+
+dgfs_status upload(dgfs_plan* P, const std::vector<char>& blob) {
+    if (hipGetDevice(&P->device) != hipSuccess) return fail(DGFS_EDEVICE, "no HIP device");
+    P->dev_bytes = blob.size();
+    if (hipMalloc(&P->dev, P->dev_bytes) != hipSuccess) {
+        P->dev = nullptr;
+        return fail(DGFS_ENOMEM, "device allocation of the plan tables failed");
     }
+    if (hipMemcpy(P->dev, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(DGFS_EDEVICE, "upload of the plan tables failed");
+    return DGFS_OK;
+}
+
+// A plan on one common grid (problem->L) that evaluates the ordered pairs set in mask.
+dgfs_status create_single(const dgfs_problem* problem, const std::vector<unsigned char>& mask, dgfs_plan** out) {
+    auto* P = new dgfs_plan();
+    P->s = problem->s;
+    P->N = problem->N;
+    P->M = problem->M;
+    P->nrho = problem->n_rho;
+    P->precision = problem->precision;
+    P->L = problem->L;
+    P->mass.assign(problem->mass, problem->mass + problem->s);
+    P->Ls.assign(problem->s, problem->L);
+    P->mask = mask;
+    dgfs::gain_geometry(P->N, P->precision, &P->geo);
+    if (problem->tile_ch != 0 || problem->tile_cz != 0) P->geo = dgfs::GainGeometry{problem->tile_ch, problem->tile_cz};
+    dgfs::pre::design(P->M, P->sigma);
+    P->antipodal = dgfs::pre::antipodal(P->sigma);
+    P->K2 = 3 * (P->N / 2) * (P->N / 2) + 1;
+    for (int i = 0; i < P->s; ++i)
+        for (int j = 0; j < P->s; ++j) P->pair.push_back(pair_params(problem, i, j));
+    // gain classes of the pairs this plan evaluates (the mask is symmetric)
+    int off = 0;
+    const double w = 4.0 * kPi / P->M;
+    for (int i = 0; i < P->s; ++i)
+        for (int j = 0; j < P->s; ++j) {
+            if (P->antipodal && j < i) continue;
+            if (!P->mask[i * P->s + j]) continue;
+            dgfs::GainClass c;
+            c.i = i;
+            c.j = j;
+            c.a = P->pair[i * P->s + j].a;
+            c.b = P->pair[i * P->s + j].b;
+            const bool half = P->antipodal && i == j;
+            c.ndir = half ? P->M / 2 : P->M;
+            c.weight = half ? 2.0 * w : w;
+            c.dir_offset = off;
+            off += c.ndir;
+            P->classes.push_back(c);
+        }
+    P->total_dirs = off;
+
+    std::vector<char> blob;
+    if (P->precision == DGFS_FP64) build_tables<double>(*P, blob);
+    else build_tables<float>(*P, blob);
+    const dgfs_status st = upload(P, blob);
+    if (st != DGFS_OK) {
+        dgfs_plan_destroy(P);
+        return st;
+    }
+    *out = P;
+    return DGFS_OK;
+}
+
+// Species-specific grids: one single-grid part per distinct pair box, with the maps that
+// carry each species onto the box and the results back (the reading of the remark after
+// eq. (domain) in Sec. 4 on independent grids per species).
+dgfs_status create_species_grids(const dgfs_problem* problem, dgfs_plan** out) {
+    const int s = problem->s;
+    auto* P = new dgfs_plan();
+    P->s = s;
+    P->N = problem->N;
+    P->M = problem->M;
+    P->nrho = problem->n_rho;
+    P->precision = problem->precision;
+    P->mass.assign(problem->mass, problem->mass + s);
+    P->Ls.assign(problem->L_species, problem->L_species + s);
+    P->L = *std::max_element(P->Ls.begin(), P->Ls.end());
+    P->mask.assign(size_t(s) * s, 1);
+    dgfs::gain_geometry(P->N, P->precision, &P->geo);
+    if (problem->tile_ch != 0 || problem->tile_cz != 0) P->geo = dgfs::GainGeometry{problem->tile_ch, problem->tile_cz};
+    std::vector<double> boxes;
+    for (int i = 0; i < s; ++i)
+        for (int j = 0; j < s; ++j) boxes.push_back(pair_box(problem, i, j));
+    std::sort(boxes.begin(), boxes.end());
+    boxes.erase(std::unique(boxes.begin(), boxes.end()), boxes.end());
+
+    std::vector<char> blob;
+    push_double(blob, P->off_minv, conserve_pack(P->mass, P->Ls, P->N));
+    auto push_map = [&](double from, double to) {
+        std::vector<double> T;
+        dgfs::pre::interpolation_matrix(P->N, from, to, T);
+        size_t off = 0;
+        if (P->precision == DGFS_FP64) push_real<double>(blob, off, T);
+        else push_real<float>(blob, off, T);
+        return static_cast<long long>(off);
+    };
+    for (double box : boxes) {
+        dgfs_plan::GridPart part;
+        part.L = box;
+        for (int i = 0; i < s; ++i) {
+            bool used = false;
+            for (int j = 0; j < s; ++j) used = used || pair_box(problem, i, j) == box;
+            if (used) part.species.push_back(i);
+        }
+        const int sg = int(part.species.size());
+        std::vector<double> m;
+        std::vector<dgfs_pair_kernel> kern;
+        std::vector<unsigned char> mask;
+        for (int k = 0; k < sg; ++k) {
+            const int i = part.species[k];
+            m.push_back(problem->mass[i]);
+            for (int l = 0; l < sg; ++l) {
+                const int j = part.species[l];
+                kern.push_back(problem->kernel[i * s + j]);
+                mask.push_back(pair_box(problem, i, j) == box ? 1 : 0);
+            }
+            part.t_in.push_back(P->Ls[i] == box ? -1 : push_map(P->Ls[i], box));
+            part.t_out.push_back(P->Ls[i] == box ? -1 : push_map(box, P->Ls[i]));
+        }
+        dgfs_problem sub = *problem;
+        sub.s = sg;
+        sub.mass = m.data();
+        sub.L = box;
+        sub.L_species = nullptr;
+        sub.kernel = kern.data();
+        const dgfs_status st = create_single(&sub, mask, &part.plan);
+        if (st != DGFS_OK) {
+            dgfs_plan_destroy(P);
+            return st;
+        }
+        P->parts.push_back(std::move(part));
+    }
+    const dgfs_status st = upload(P, blob);
+    if (st != DGFS_OK) {
+        dgfs_plan_destroy(P);
+        return st;
+    }
+    *out = P;
+    return DGFS_OK;
+}
+
+// Byte layout of one part's share of the workspace for nb nodes.
+struct PartLayout {
+    size_t sub, X, Y, tmp, total;
+};
+
+PartLayout part_layout(const dgfs_plan& P, const dgfs_plan::GridPart& part, int64_t nb, bool pairs) {
+    const size_t E = P.elem() * P.n3() * size_t(nb);
+    const size_t sg = part.species.size();
+    PartLayout l;
+    l.sub = 0;
+    l.X = detail_align(part.plan->ws_per_node(pairs) * size_t(nb) + part.plan->ws_slack());
+    l.Y = l.X + detail_align(E * sg);
+    l.tmp = l.Y + detail_align(E * (pairs ? sg * sg : sg));
+    l.total = l.tmp + detail_align(2 * E);
+    return l;
+}
+
+// One slice of nb nodes through every part.  stage_ms (optional, synchronous): adds the
+// part's stage times, with the moves between grids counted in the first and last stage.
+dgfs_status run_parts(const dgfs_plan& P, const void* f, void* Q, int64_t nb, void* ws, bool pairs, hipStream_t st,
+                      hipEvent_t* ev, float* stage_ms) {
+    const size_t E = P.elem();
+    const int64_t n3 = int64_t(P.n3());
+    const int s = P.s;
+    const char* dev = static_cast<const char*>(P.dev);
+    std::vector<unsigned char> written(s, 0);
+    for (const auto& part : P.parts) {
+        const int sg = int(part.species.size());
+        const PartLayout lay = part_layout(P, part, nb, pairs);
+        char* w = static_cast<char*>(ws);
+        char* X = w + lay.X;
+        char* Y = w + lay.Y;
+        char* tmp = w + lay.tmp;
+        auto map = [&](long long off) { return off < 0 ? nullptr : static_cast<const void*>(dev + off); };
+        auto ok = [](hipError_t e) { return e == hipSuccess; };
+        if (ev) hipEventRecord(ev[6], st);
+        for (int k = 0; k < sg; ++k) {
+            const int i = part.species[k];
+            if (!ok(dgfs::launch_move(P, static_cast<const char*>(f) + size_t(i) * n3 * E, int64_t(s) * n3,
+                                      X + size_t(k) * n3 * E, int64_t(sg) * n3, map(part.t_in[k]), nb, false, tmp, st)))
+                return fail(DGFS_EDEVICE, "kernel launch failed (grid move)");
+        }
+        hipError_t e = dgfs::launch_collide(*part.plan, X, Y, nb, w + lay.sub, pairs, st, ev);
+        if (e != hipSuccess) return fail(DGFS_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+        for (int k = 0; k < sg; ++k) {
+            const int i = part.species[k];
+            if (!pairs) {
+                if (!ok(dgfs::launch_move(P, Y + size_t(k) * n3 * E, int64_t(sg) * n3,
+                                          static_cast<char*>(Q) + size_t(i) * n3 * E, int64_t(s) * n3,
+                                          map(part.t_out[k]), nb, written[i] != 0, tmp, st)))
+                    return fail(DGFS_EDEVICE, "kernel launch failed (grid move)");
+                written[i] = 1;
+                continue;
+            }
+            for (int l = 0; l < sg; ++l) {
+                const int j = part.species[l];
+                if (!part.plan->mask[k * sg + l]) continue;
+                if (!ok(dgfs::launch_move(P, Y + size_t(k * sg + l) * n3 * E, int64_t(sg) * sg * n3,
+                                          static_cast<char*>(Q) + size_t(i * s + j) * n3 * E, int64_t(s) * s * n3,
+                                          map(part.t_out[k]), nb, false, tmp, st)))
+                    return fail(DGFS_EDEVICE, "kernel launch failed (grid move)");
+            }
+        }
+        if (ev) {
+            hipEventRecord(ev[7], st);
+            if (hipEventSynchronize(ev[7]) != hipSuccess) return fail(DGFS_EDEVICE, "hipEventSynchronize failed");
+            float ms = 0.0f;
+            hipEventElapsedTime(&ms, ev[6], ev[1]);
+            stage_ms[0] += ms;
+            for (int k = 1; k < 4; ++k) {
+                hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+                stage_ms[k] += ms;
+            }
+            hipEventElapsedTime(&ms, ev[4], ev[7]);
+            stage_ms[4] += ms;
+        }
+    }
+    return DGFS_OK;
 }
 
 }  // namespace
 
 size_t dgfs_plan::ws_per_node(bool pairs) const {
+    if (!parts.empty()) {
+        // per node, the largest part (its layout for one node, less its one-off slack)
+        size_t best = 0;
+        for (const auto& part : parts) {
+            const size_t sg = part.species.size(), E = elem() * n3();
+            best = std::max(best, part.plan->ws_per_node(pairs) + E * (sg + (pairs ? sg * sg : sg) + 2));
+        }
+        return best;
+    }
     const size_t c = 2 * elem() * n3();
     const int nslots = pairs ? s * s : s;
     return c * (size_t(s) + classes.size() * size_t(nrho) + 2 * size_t(nslots));
@@ -398,7 +655,7 @@ dgfs_status dgfs_pair_tables(const dgfs_problem* problem, int32_t i, int32_t j, 
     if (loss) {
         const int K2 = 3 * (problem->N / 2) * (problem->N / 2) + 1;
         for (int k2 = 0; k2 < K2; ++k2)
-            loss[k2] = dgfs::pre::loss_weight(std::sqrt(double(k2)), pp.R, pp.gamma, pp.C, problem->L);
+            loss[k2] = dgfs::pre::loss_weight(std::sqrt(double(k2)), pp.R, pp.gamma, pp.C, pair_box(problem, i, j));
     }
     return DGFS_OK;
 }
@@ -407,65 +664,21 @@ dgfs_status dgfs_plan_create(const dgfs_problem* problem, dgfs_plan** out) {
     if (!out) return fail(DGFS_EINVAL, "out is NULL");
     dgfs_status st = check(problem);
     if (st != DGFS_OK) return st;
-    auto* P = new dgfs_plan();
-    P->s = problem->s;
-    P->N = problem->N;
-    P->M = problem->M;
-    P->nrho = problem->n_rho;
-    P->precision = problem->precision;
-    P->L = problem->L;
-    P->mass.assign(problem->mass, problem->mass + problem->s);
-    dgfs::gain_geometry(P->N, P->precision, &P->geo);
-    if (problem->tile_ch != 0 || problem->tile_cz != 0) P->geo = dgfs::GainGeometry{problem->tile_ch, problem->tile_cz};
-    dgfs::pre::design(P->M, P->sigma);
-    P->antipodal = dgfs::pre::antipodal(P->sigma);
-    P->K2 = 3 * (P->N / 2) * (P->N / 2) + 1;
-    for (int i = 0; i < P->s; ++i)
-        for (int j = 0; j < P->s; ++j) P->pair.push_back(pair_params(problem, i, j));
-    // gain classes
-    int off = 0;
-    const double w = 4.0 * kPi / P->M;
-    for (int i = 0; i < P->s; ++i)
-        for (int j = 0; j < P->s; ++j) {
-            if (P->antipodal && j < i) continue;
-            dgfs::GainClass c;
-            c.i = i;
-            c.j = j;
-            c.a = P->pair[i * P->s + j].a;
-            c.b = P->pair[i * P->s + j].b;
-            const bool half = P->antipodal && i == j;
-            c.ndir = half ? P->M / 2 : P->M;
-            c.weight = half ? 2.0 * w : w;
-            c.dir_offset = off;
-            off += c.ndir;
-            P->classes.push_back(c);
-        }
-    P->total_dirs = off;
-
-    std::vector<char> blob;
-    if (P->precision == DGFS_FP64) build_tables<double>(*P, blob);
-    else build_tables<float>(*P, blob);
-
-    if (hipGetDevice(&P->device) != hipSuccess) {
-        delete P;
-        return fail(DGFS_EDEVICE, "no HIP device");
+    bool one_box = true;
+    if (problem->L_species)
+        for (int i = 1; i < problem->s; ++i) one_box = one_box && problem->L_species[i] == problem->L_species[0];
+    if (!one_box) return create_species_grids(problem, out);
+    dgfs_problem single = *problem;
+    if (problem->L_species) {
+        single.L = problem->L_species[0];
+        single.L_species = nullptr;
     }
-    P->dev_bytes = blob.size();
-    if (hipMalloc(&P->dev, P->dev_bytes) != hipSuccess) {
-        delete P;
-        return fail(DGFS_ENOMEM, "device allocation of the plan tables failed");
-    }
-    if (hipMemcpy(P->dev, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
-        hipFree(P->dev);
-        delete P;
-        return fail(DGFS_EDEVICE, "upload of the plan tables failed");
-    }
-    *out = P;
-    return DGFS_OK;
+    return create_single(&single, std::vector<unsigned char>(size_t(problem->s) * problem->s, 1), out);
 }
 
 void dgfs_plan_destroy(dgfs_plan* plan) {
     if (!plan) return;
+    for (auto& part : plan->parts) dgfs_plan_destroy(part.plan);
     if (plan->dev) hipFree(plan->dev);
     delete plan;
 }
@@ -475,7 +688,7 @@ dgfs_status dgfs_workspace_size(const dgfs_plan* plan, int64_t batch, size_t* by
     if (batch < 1) return fail(DGFS_EINVAL, "batch must be >= 1");
     // the pair-resolved mode needs the larger slot set; size for it (and at least what
     // the plain FP64 path needs for one node)
-    *bytes = std::max(plan->ws_per_node(true) * size_t(batch) + 4 * 256, dgfs::plain_ws_bytes(*plan) + 256);
+    *bytes = std::max(plan->ws_per_node(true) * size_t(batch) + plan->ws_slack(), dgfs::plain_ws_bytes(*plan) + 256);
     return DGFS_OK;
 }
 
@@ -487,13 +700,13 @@ static dgfs_status collide_impl(const dgfs_plan* plan, const void* f, void* Q, i
     if (!f || !Q || !ws) return fail(DGFS_EINVAL, "f, Q and workspace are required");
     if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(DGFS_EINVAL, "workspace must be 256-byte aligned");
     const size_t per = plan->ws_per_node(pairs);
-    if (ws_bytes < per + 4 * 256) return fail(DGFS_ENOMEM, "workspace smaller than one node");
-    const int64_t slice = std::min<int64_t>(batch, int64_t((ws_bytes - 4 * 256) / per));
+    if (ws_bytes < per + plan->ws_slack()) return fail(DGFS_ENOMEM, "workspace smaller than one node");
+    const int64_t slice = std::min<int64_t>(batch, int64_t((ws_bytes - plan->ws_slack()) / per));
     const int nslots = pairs ? plan->s * plan->s : plan->s;
     const size_t in_stride = size_t(plan->s) * plan->n3() * plan->elem();
     const size_t out_stride = size_t(nslots) * plan->n3() * plan->elem();
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipEvent_t ev[6] = {};
+    hipEvent_t ev[8] = {};
     if (stage_ms) {
         for (int k = 0; k < 5; ++k) stage_ms[k] = 0.0f;
         for (auto& e : ev)
@@ -502,6 +715,13 @@ static dgfs_status collide_impl(const dgfs_plan* plan, const void* f, void* Q, i
     dgfs_status result = DGFS_OK;
     for (int64_t b0 = 0; b0 < batch; b0 += slice) {
         const int64_t nb = std::min(slice, batch - b0);
+        if (!plan->parts.empty()) {
+            result = run_parts(*plan, static_cast<const char*>(f) + b0 * in_stride,
+                               static_cast<char*>(Q) + b0 * out_stride, nb, ws, pairs, st, stage_ms ? ev : nullptr,
+                               stage_ms);
+            if (result != DGFS_OK) break;
+            continue;
+        }
         hipError_t e = dgfs::launch_collide(*plan, static_cast<const char*>(f) + b0 * in_stride,
                                             static_cast<char*>(Q) + b0 * out_stride, nb, ws, pairs, st,
                                             stage_ms ? ev : nullptr);
@@ -546,6 +766,7 @@ dgfs_status dgfs_collide_plain(const dgfs_plan* plan, const double* f, double* Q
                                size_t ws_bytes, void* stream) {
     if (!plan) return fail(DGFS_EINVAL, "plan is NULL");
     if (plan->precision != DGFS_FP64) return fail(DGFS_EUNSUPPORTED, "the plain path needs an FP64 plan");
+    if (!plan->parts.empty()) return fail(DGFS_EUNSUPPORTED, "the plain path has one common grid");
     if (batch < 0) return fail(DGFS_EINVAL, "batch must be >= 0");
     if (batch == 0) return DGFS_OK;
     if (!f || !Q || !workspace) return fail(DGFS_EINVAL, "f, Q and workspace are required");
@@ -721,6 +942,17 @@ dgfs_status dgfs_graph_launch(void* graph, void* stream) {
 
 void dgfs_graph_destroy(void* graph) {
     if (graph) hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph));
+}
+
+dgfs_status dgfs_interpolation_matrix(int32_t N, double L_from, double L_to, double* T) {
+    if (!T) return fail(DGFS_EINVAL, "T is required");
+    if (N < 2 || N % 2 != 0 || N > 1024) return fail(DGFS_EINVAL, "N must be even and in [2, 1024]");
+    if (!(L_from > 0.0) || !(L_to > 0.0) || !std::isfinite(L_from) || !std::isfinite(L_to))
+        return fail(DGFS_EINVAL, "half-widths must be positive");
+    std::vector<double> m;
+    dgfs::pre::interpolation_matrix(N, L_from, L_to, m);
+    std::copy(m.begin(), m.end(), T);
+    return DGFS_OK;
 }
 
 const char* dgfs_status_string(dgfs_status status) {

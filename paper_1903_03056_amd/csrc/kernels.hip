@@ -27,14 +27,15 @@ namespace dgfs {
 
 // ========================================================= FP64 conservation
 // One workgroup per node: the s+4 invariants A Q in FP64, lambda = (A A^T)^{-1} A Q,
-// then Q_out = Q - A^T lambda.  Rows of A: h^3 on species i (s rows), m_i h^3 v_d
-// (3 rows), m_i h^3 |v|^2 (1 row).
+// then Q_out = Q - A^T lambda.  Rows of A: h_i^3 on species i (s rows), m_i h_i^3 v_d
+// (3 rows), m_i h_i^3 |v|^2 (1 row), on species i's own grid (half-width Ls[i]).
 // With UPDATE, the projected value is not stored but added to the state:
 // f <- f + dt * Q_projected (forward-Euler step of a homogeneous relaxation).
 template <typename TIN, bool UPDATE>
 __global__ __launch_bounds__(1024) void conserve_kernel(const TIN* Q, double* out, TIN* fstate, double dt,
                                                         const double* __restrict__ Minv,
-                                                        const double* __restrict__ mass, int s, int N, double L) {
+                                                        const double* __restrict__ mass,
+                                                        const double* __restrict__ Ls, int s, int N) {
     constexpr int R = 12;  // s + 4 <= 12
     __shared__ double red[16][R];
     __shared__ double lam[R];
@@ -43,7 +44,6 @@ __global__ __launch_bounds__(1024) void conserve_kernel(const TIN* Q, double* ou
     const TIN* q = Q + int64_t(b) * tot;
     double* o = UPDATE ? nullptr : out + int64_t(b) * tot;
     TIN* fs = UPDATE ? fstate + int64_t(b) * tot : nullptr;
-    const double h = 2.0 * L / N, h3 = h * h * h;
     const int nr = s + 4;
     double acc[R];
 #pragma unroll
@@ -51,6 +51,7 @@ __global__ __launch_bounds__(1024) void conserve_kernel(const TIN* Q, double* ou
     for (int64_t idx = threadIdx.x; idx < tot; idx += 1024) {
         const int i = int(idx / n3);
         const int n = int(idx - int64_t(i) * n3);
+        const double L = Ls[i], h = 2.0 * L / N, h3 = h * h * h;
         const double vx = -L + (n / (N * N)) * h, vy = -L + ((n / N) % N) * h, vz = -L + (n % N) * h;
         const double val = double(q[idx]);
         const double mh = mass[i] * h3 * val;
@@ -94,6 +95,7 @@ __global__ __launch_bounds__(1024) void conserve_kernel(const TIN* Q, double* ou
     for (int64_t idx = threadIdx.x; idx < tot; idx += 1024) {
         const int i = int(idx / n3);
         const int n = int(idx - int64_t(i) * n3);
+        const double L = Ls[i], h = 2.0 * L / N, h3 = h * h * h;
         const double vx = -L + (n / (N * N)) * h, vy = -L + ((n / N) % N) * h, vz = -L + (n % N) * h;
         const double mh = mass[i] * h3;
         const double corr = lam[i] * h3 + mh * (lam[s] * vx + lam[s + 1] * vy + lam[s + 2] * vz +
@@ -147,23 +149,24 @@ hipError_t launch_conserve(const dgfs_plan& p, const void* Q, double* out, void*
     const char* dev = static_cast<const char*>(p.dev);
     const double* minv = reinterpret_cast<const double*>(dev + p.off_minv);
     const double* mass = minv + (p.s + 4) * (p.s + 4);
+    const double* Ls = mass + p.s;
     const dim3 grid(static_cast<unsigned>(nb)), block(1024);
     if (p.precision == DGFS_FP64) {
         if (fstate)
             conserve_kernel<double, true><<<grid, block, 0, st>>>(static_cast<const double*>(Q), nullptr,
-                                                                  static_cast<double*>(fstate), dt, minv, mass, p.s,
-                                                                  p.N, p.L);
+                                                                  static_cast<double*>(fstate), dt, minv, mass, Ls,
+                                                                  p.s, p.N);
         else
             conserve_kernel<double, false><<<grid, block, 0, st>>>(static_cast<const double*>(Q), out, nullptr, 0.0,
-                                                                   minv, mass, p.s, p.N, p.L);
+                                                                   minv, mass, Ls, p.s, p.N);
     } else {
         if (fstate)
             conserve_kernel<float, true><<<grid, block, 0, st>>>(static_cast<const float*>(Q), nullptr,
-                                                                 static_cast<float*>(fstate), dt, minv, mass, p.s,
-                                                                 p.N, p.L);
+                                                                 static_cast<float*>(fstate), dt, minv, mass, Ls,
+                                                                 p.s, p.N);
         else
             conserve_kernel<float, false><<<grid, block, 0, st>>>(static_cast<const float*>(Q), out, nullptr, 0.0,
-                                                                  minv, mass, p.s, p.N, p.L);
+                                                                  minv, mass, Ls, p.s, p.N);
     }
     return hipGetLastError();
 }

@@ -55,8 +55,10 @@ struct SlotSet {
 
 struct dgfs_plan {
     int s = 0, N = 0, M = 0, nrho = 0, precision = 0;
-    double L = 0;
+    double L = 0;               // box half-width (the widest box with species-specific grids)
     std::vector<double> mass;
+    std::vector<double> Ls;     // [s] half-width of each species' grid
+    std::vector<unsigned char> mask;  // [s*s] ordered pairs evaluated by this plan
     dgfs::GainGeometry geo{};
     std::vector<double> sigma;  // design, [M][3]
     bool antipodal = false;
@@ -75,10 +77,22 @@ struct dgfs_plan {
     // plain per-point FP64 path (FP64 plans only): phases [s*s][nrho][M][2][3][N], F [s*s][nrho][K2]
     size_t off_plain_ph = 0, off_plain_F = 0;
 
+    // Species-specific grids: one single-grid sub-plan per distinct pair box L_ij, each
+    // evaluating the ordered pairs whose wider box it is.  Empty for a single-grid plan.
+    struct GridPart {
+        dgfs_plan* plan = nullptr;
+        double L = 0;
+        std::vector<int> species;         // global index of each local species
+        std::vector<long long> t_in;      // byte offset in `dev` of the map own grid -> L, or -1
+        std::vector<long long> t_out;     // byte offset in `dev` of the map L -> own grid, or -1
+    };
+    std::vector<GridPart> parts;
+
     size_t elem() const { return precision == DGFS_FP64 ? sizeof(double) : sizeof(float); }
     size_t n3() const { return size_t(N) * N * N; }
-    // workspace bytes per node
+    // workspace bytes per node, and the alignment slack added once per call
     size_t ws_per_node(bool pairs) const;
+    size_t ws_slack() const { return parts.empty() ? 4 * 256 : 12 * 256; }
 };
 
 namespace dgfs {
@@ -89,6 +103,11 @@ hipError_t launch_collide(const dgfs_plan& p, const void* f, void* Q, int64_t nb
 // out != NULL: out = projection of Q (FP64); fstate != NULL: fstate += dt * projection.
 hipError_t launch_conserve(const dgfs_plan& p, const void* Q, double* out, void* fstate, double dt, int64_t nb,
                            hipStream_t stream);
+// Copy (Tm == NULL) or interpolate (Tm = [N][N] one-dimensional map, applied along each
+// axis) nb fields of N^3 values with per-node strides (in elements), storing or adding.
+// tmp: 2 nb N^3 values of scratch.
+hipError_t launch_move(const dgfs_plan& p, const void* in, int64_t in_stride, void* out, int64_t out_stride,
+                       const void* Tm, int64_t nb, bool accumulate, void* tmp, hipStream_t stream);
 // Plain per-point FP64 path (plain.hip).
 size_t plain_ws_bytes(const dgfs_plan& p);
 hipError_t launch_collide_plain(const dgfs_plan& p, const double* f, double* Q, int64_t nb, void* ws,

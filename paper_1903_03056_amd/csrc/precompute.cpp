@@ -202,5 +202,28 @@ double loss_weight(double mabs, double R, double gamma, double C, double L) {
     return 16.0 * kPi * kPi * C * cur;
 }
 
+void interpolation_matrix(int N, double L_from, double L_to, std::vector<double>& T) {
+    T.assign(size_t(N) * N, 0.0);
+    const double h_from = 2.0 * L_from / N, h_to = 2.0 * L_to / N;
+    for (int r = 0; r < N; ++r) {
+        const double v = -L_to + r * h_to;
+        if (!(v >= -L_from && v < L_from)) continue;
+        for (int n = 0; n < N; ++n) {
+            const double vn = -L_from + n * h_from;
+            double acc = 0.0;
+            for (int j = 0; j < N; ++j) {
+                const int k = j < N / 2 ? j : j - N;
+                // c_k(v) e^{-i pi k v_n / L}; the Nyquist mode uses cos(pi N v / 2L)
+                const double an = -kPi * k * vn / L_from;
+                if (k == -N / 2)
+                    acc += std::cos(kPi * (N / 2) * v / L_from) * std::cos(an);
+                else
+                    acc += std::cos(kPi * k * v / L_from + an);
+            }
+            T[size_t(r) * N + n] = acc / N;
+        }
+    }
+}
+
 }  // namespace pre
 }  // namespace dgfs

@@ -35,5 +35,11 @@ double kernel_mode(double kabs, double rho, double a, double gamma, double C, do
 // the panel count is doubled until two values agree to 1e-15 of the integrand scale.
 double loss_weight(double mabs, double R, double gamma, double C, double L);
 
+// One-dimensional map between two grids of N points, v_n = -L + n 2L/N: row n' holds the
+// weights that evaluate, at point n' of the grid L_to, the real trigonometric interpolant
+// of samples on the grid L_from (modes -N/2..N/2-1, the Nyquist mode split evenly between
+// +N/2 and -N/2).  Rows of points outside [-L_from, L_from) are zero.  T is [N][N].
+void interpolation_matrix(int N, double L_from, double L_to, std::vector<double>& T);
+
 }  // namespace pre
 }  // namespace dgfs

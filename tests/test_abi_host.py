@@ -62,7 +62,9 @@ def test_check_problem_accepts_and_rejects():
     assert check_problem(m, 6.0, 20, 12, 16, k) == DGFS_EUNSUPPORTED     # no kernels for N=20
     assert check_problem(m, 6.0, 32, 12, 16, k, "f64") == DGFS_OK
     assert check_problem(m, 6.0, 48, 24, 24, k) == DGFS_OK
-    assert check_problem(m, 6.0, 32, 12, 16, k, L_species=(6.0, 1.0)) == DGFS_EUNSUPPORTED
+    assert check_problem(m, 6.0, 32, 12, 16, k, L_species=(6.0, 1.0)) == DGFS_OK
+    assert check_problem(m, 6.0, 32, 12, 16, k, L_species=(6.0, -1.0)) == DGFS_EINVAL
+    assert check_problem(m, -1.0, 32, 12, 16, k, L_species=(6.0, 1.0)) == DGFS_OK   # L ignored
 
 
 def test_plan_create_without_device_reports_error():
@@ -122,3 +124,32 @@ def test_tile_candidates_and_validation():
     for tile in tile_candidates(32, "f32"):
         assert check_problem(m, 6.0, 32, 12, 16, k, tile=tile) == DGFS_OK
     assert check_problem(m, 6.0, 32, 12, 16, k, tile=(3, 1)) == DGFS_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("N,L_from,L_to", [(8, 1.0, 2.3), (16, 1.0484, 6.0), (24, 6.0, 1.0484), (48, 2.0, 2.0)])
+def test_interpolation_matrix_matches_oracle(N, L_from, L_to):
+    """The library's one-dimensional map, applied along each axis, gives the oracle's
+    interpolant between species grids (which it computes from the Fourier coefficients)."""
+    from oracle import grids as OG
+    from paper_1903_03056_amd import interpolation_matrix
+    T = interpolation_matrix(N, L_from, L_to)
+    f = np.random.default_rng(N).random((N, N, N))
+    got = np.einsum("ai,bj,ck,ijk->abc", T, T, T, f, optimize=True)
+    ref = OG.interpolate(f, L_from, L_to)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(f).max()
+
+
+def test_pair_tables_use_the_pair_box_with_species_grids():
+    """With species-specific grids, R_ij and G-_ij are those of the box max(L_i, L_j)."""
+    from paper_1903_03056_amd import pair_tables
+    masses = (1.0, 32.75)
+    Ls = (6.0, 6.0 * np.sqrt(1.0 / 32.75))
+    k = _kern(masses, 0.5)
+    for i in range(2):
+        for j in range(2):
+            t = pair_tables(masses, 6.0, 16, 24, 8, k, i, j, L_species=Ls)
+            Lij = max(Ls[i], Ls[j])
+            assert t["R"] == pytest.approx(OP.truncation_radius(Lij, masses[i], masses[j]), rel=1e-15)
+            k2 = np.arange(3 * 8 ** 2 + 1)
+            ref = OS.loss_weight(np.sqrt(k2), t["R"], t["gamma"], t["C"], Lij)
+            assert np.abs(t["loss_by_k2"] - ref).max() <= 1e-13 * np.abs(ref).max()
