@@ -7,6 +7,14 @@ the whole hot path: forward transforms, gain (rho, sigma) loop, radial sum and l
 inverse transforms and combination (dgfs_collide), then the FP64 conservation
 projection (dgfs_conserve).  Inputs are resident in device memory before timing.
 
+Also measured, outside the timed steps (the "workloads" object):
+  * uneven batch: 512 nodes at N=24, 256 at N=32 and 64 at N=48, 3 species (1, 2, 4),
+    N_rho = N/2, autotuned gain-kernel tiles, the whole batch captured once in a hipGraph
+    and replayed (per-replay p50/p99);
+  * heavy/light species-specific grids: 1024 nodes, masses (1, 32.75) on boxes
+    L_i = 6 sqrt(1/m_i), hard spheres, N=48, M=24 (7-design), N_rho=24;
+  * measured ceilings: a device copy (HBM) and an FMA loop (FP32 vector).
+
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 from __future__ import annotations
@@ -84,14 +92,130 @@ def cpu_baseline(f64, max_seconds=12.0):
                       f"({dt:.1f} s)"}, outs
 
 
+def measured_peaks(torch, dev):
+    """A 1 GiB device copy (HBM read + write) and the library's FMA-loop probe."""
+    import ctypes
+
+    from paper_1903_03056_amd import _lib
+    n = 256 * 1024 * 1024
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 5 * 2 * n * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    blocks, iters = 256 * 16, 2048
+    scratch = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    tf = ctypes.c_double()
+    lib = _lib.load()
+    _lib.check(lib.dgfs_probe_valu(ctypes.c_void_p(scratch.data_ptr()), scratch.numel() * 4, blocks, iters,
+                                   ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream), ctypes.byref(tf)),
+               "dgfs_probe_valu")
+    return {"hbm_copy_GBps": round(copy_gbps, 1), "valu_fp32_fma_TFLOPs": round(tf.value, 2),
+            "note": "copy: 5 x 1 GiB device-to-device, read+write bytes; FMA loop: unpacked FP32 FMA chains"}
+
+
+def group_leg(torch, dev, replays):
+    """Uneven batch of three N-classes in one hipGraph (autotuned tiles)."""
+    from paper_1903_03056_amd import CollisionGroup, CollisionPlan
+    from synth import inputs as I
+    cfg = I.config(4)
+    masses, s, L, M, omega = cfg["masses"], cfg["s"], cfg["L"], cfg["M"], cfg["omega"]
+    rng = np.random.default_rng(cfg["seed"])
+    plans, fs, host = [], [], []
+    t0 = time.perf_counter()
+    for N, B in cfg["groups"]:
+        plans.append(CollisionPlan(masses, N, L, M, N // 2, omega=omega, precision="f32", tile="auto"))
+        h = I.draw_bimaxwellian_batch(rng, B, s, N, L, masses).astype(np.float32)
+        host.append(h)
+        fs.append(torch.tensor(h, device=dev))
+    setup_s = time.perf_counter() - t0
+    group = CollisionGroup(plans)
+    graph, outs = group.capture(fs)
+    for _ in range(2):
+        graph.launch()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(replays)]
+    for e0, e1 in evs:
+        e0.record(graph.stream)
+        graph.launch()
+        e1.record(graph.stream)
+    torch.cuda.synchronize()
+    ms = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    evals = sum(B * s * s for _, B in cfg["groups"])
+    flops = sum(B * gain_flops_per_node(N, M, N // 2, s) for N, B in cfg["groups"])
+    res = {"workload": "uneven batch: 512 nodes N=24 + 256 N=32 + 64 N=48, 3 species m=(1,2,4), VHS "
+                       "omega=0.74, L=6, M=12, N_rho=N/2, bi-Maxwellians, seed 4; one hipGraph replay per call",
+           "value": round(evals / (ms.mean() * 1e-3), 1), "unit": "evals/s", "replays": replays,
+           "ms_per_call": {"mean": round(float(ms.mean()), 3), "p50": round(float(np.percentile(ms, 50)), 3),
+                           "p99": round(float(np.percentile(ms, 99)), 3)},
+           "gain_tflops_over_call": round(flops / (ms.mean() * 1e-3) / 1e12, 2),
+           "tiles": {str(p.N): list(p.tile) if p.tile else None for p in plans},
+           "setup_s_incl_autotune": round(setup_s, 1)}
+    # node 0 of the N=24 and N=32 classes, for the oracle comparison of the CPU leg
+    checks = [dict(leg="uneven_group_graph", key=str(N), f=host[k][0].astype(np.float64),
+                   got=outs[k][0].double().cpu().numpy(), masses=masses, omega=omega, Ls=(L,) * s, N=N, M=M,
+                   nrho=N // 2) for k, (N, B) in enumerate(cfg["groups"][:2])]
+    graph.close()
+    group.close()
+    return res, checks
+
+
+def species_grid_leg(torch, dev, calls):
+    """1024 heavy/light nodes on species-specific grids, N=48, M=24, N_rho=24."""
+    from paper_1903_03056_amd import CollisionPlan
+    from synth import inputs as I
+    cfg = I.config(3)
+    masses, N, M, nrho, B = cfg["masses"], cfg["N"], cfg["M"], cfg["nrho"], cfg["batch"]
+    Ls = tuple(cfg["L"] * math.sqrt(1.0 / m) for m in masses)
+    f = I.draw_config3_batch(np.random.default_rng(cfg["seed"]), B, N, Ls, masses).astype(np.float32)
+    t0 = time.perf_counter()
+    plan = CollisionPlan(masses, N, Ls, M, nrho, omega=cfg["omega"], precision="f32", tile="auto")
+    setup_s = time.perf_counter() - t0
+    ft = torch.tensor(f, device=dev)
+    ws = torch.empty(plan.workspace_bytes(256), dtype=torch.uint8, device=dev)
+    Q = torch.empty_like(ft)
+    plan.collide(ft, out=Q, workspace=ws)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream(dev)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+    for e0, e1 in evs:
+        e0.record(st)
+        plan.collide(ft, out=Q, workspace=ws)
+        e1.record(st)
+    torch.cuda.synchronize()
+    ms = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    s = len(masses)
+    flops = B * gain_flops_per_node(N, M, nrho, s, antipodal=False)
+    res = {"workload": "heavy/light: 1024 nodes, m=(1,32.75) on species grids L=(6, 1.0484), hard spheres, "
+                       "N=48, M=24 (7-design), N_rho=24, Maxwellians at rest, seed 3; 256-node workspace slices",
+           "value": round(B * s * s / (ms.mean() * 1e-3), 1), "unit": "evals/s", "calls": calls,
+           "ms_per_call": {"mean": round(float(ms.mean()), 2), "p50": round(float(np.percentile(ms, 50)), 2),
+                           "p99": round(float(np.percentile(ms, 99)), 2)},
+           "gain_tflops_over_call": round(flops / (ms.mean() * 1e-3) / 1e12, 2),
+           "tile": list(plan.tile) if plan.tile else None, "setup_s_incl_autotune": round(setup_s, 1)}
+    # the last node (in the ragged final slice), for the oracle comparison of the CPU leg
+    checks = [dict(leg="heavy_light_species_grids", key="last node", f=f[B - 1].astype(np.float64),
+                   got=Q[B - 1].double().cpu().numpy(), masses=masses, omega=cfg["omega"], Ls=Ls, N=N, M=M,
+                   nrho=nrho)]
+    return res, checks
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true",
                     help="leave out the plain per-point FP64 comparison leg (not part of the timed step)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="leave out the uneven-batch, species-grid and measured-ceiling legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain device copy of 2 x 256 MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -130,6 +254,7 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: {src.numel() * 4} bytes read + {dst.numel() * 4} bytes written")
         del src, dst
+    log(f"slab: {args.warmup} warm-up and {args.steps} timed steps")
     for _ in range(args.warmup):
         plan.collide(f, out=Q, workspace=ws)
         plan.conserve(Q, out=Qc)
@@ -198,9 +323,12 @@ def main():
                               "bytes_per_launch": cons_bytes},
         "precompute_s": round(precompute_s, 3),
     }
+    Qh = Q.double().cpu().numpy()
+    Qch = Qc[:4].cpu().numpy()
     # the plain per-point FP64 GPU path on the first nodes of the same workload
     plain_nodes = 0 if args.no_plain else 2
     if plain_nodes:
+        log("plain FP64 path")
         plan64 = CollisionPlan(w["masses"], w["N"], w["L"], w["M"], w["n_rho"], omega=w["omega"], precision="f64")
         f64d = torch.tensor(f32[:plain_nodes].astype(np.float64), device=dev)
         Qp = plan64.collide_plain(f64d[:1])          # warm-up
@@ -211,20 +339,49 @@ def main():
         plain_s = time.perf_counter() - t0
         out["plain_fp64_path"] = {"value": round(plain_nodes * s * s / plain_s, 2), "unit": "evals/s",
                                   "sample": f"first {plain_nodes} nodes, one node per pass, unfused FP64 kernels"}
+    if not args.no_extra:
+        log("measured ceilings")
+        peaks = measured_peaks(torch, dev)
+        out["measured_peaks"] = peaks
+        out["roofline"]["frac_of_measured_fma"] = round(achieved / peaks["valu_fp32_fma_TFLOPs"], 4)
+        log("uneven batch in one graph")
+        extra, checks = {}, []
+        extra["uneven_group_graph"], c = group_leg(torch, dev, 20)
+        checks += c
+        log("species-specific grids")
+        extra["heavy_light_species_grids"], c = species_grid_leg(torch, dev, 3)
+        checks += c
+        out["workloads"] = extra
+    else:
+        checks = []
 
     def rel_err(a, ref):
         num = np.abs(a - ref).reshape(s, -1).max(1)
         return float(np.max(num / np.abs(ref).reshape(s, -1).max(1)))
 
     if not args.no_cpu_baseline:
+        log("oracle on the host cores")
+        from oracle import moments as OM
         base, outs = cpu_baseline(f32.astype(np.float64))
         out["cpu_baseline"] = base
-        Qh = Q.double().cpu().numpy()
         out["max_rel_linf_vs_oracle"] = max(rel_err(Qh[b], ref) for b, ref in enumerate(outs))
+        out["conservation_residual_after_fp64_projection"] = float(max(
+            OM.conservation_residual(Qch[b], w["masses"], (w["L"],) * s).max() for b in range(Qch.shape[0])))
         if plain_nodes:
             Qph = Qp.cpu().numpy()
             out["plain_fp64_path"]["max_rel_linf_vs_oracle"] = max(
                 rel_err(Qph[b], outs[b]) for b in range(min(plain_nodes, len(outs))))
+        # sampled nodes of the other workloads against the oracle
+        from oracle import grids as OG, spectral as OS
+        for c in checks:
+            prob = OS.vhs_problem(c["masses"], c["omega"], c["Ls"][0], c["N"], c["M"], c["nrho"])
+            if len(set(c["Ls"])) > 1:
+                ref = OG.collide(c["f"], prob, c["Ls"])
+            else:
+                ref = OS.collide(c["f"], prob)
+            ns = len(c["masses"])
+            err = float(np.max(np.abs(c["got"] - ref).reshape(ns, -1).max(1) / np.abs(ref).reshape(ns, -1).max(1)))
+            out["workloads"][c["leg"]].setdefault("max_rel_linf_vs_oracle", {})[c["key"]] = err
     print(json.dumps(out), flush=True)
 
 

@@ -213,6 +213,14 @@ dgfs_status dgfs_design(int32_t M, double* sigma);
  * along each axis.  T: [N][N] host doubles.  No device is touched. */
 dgfs_status dgfs_interpolation_matrix(int32_t N, double L_from, double L_to, double* T);
 
+/* Measurement aid: the attainable FP32 vector FMA rate of the current device (the
+ * ceiling the kernels' arithmetic can reach, stated beside the datasheet peak).  Runs
+ * `blocks` workgroups of 256 threads, each thread `iters` x 8 independent FMAs, once to
+ * warm up and once timed with HIP events on `stream` (synchronous).  scratch: device
+ * memory of at least blocks * 256 floats.  *tflops receives the measured rate. */
+dgfs_status dgfs_probe_valu(void* scratch, size_t scratch_bytes, int32_t blocks, int32_t iters, void* stream,
+                            double* tflops);
+
 const char* dgfs_status_string(dgfs_status status);
 const char* dgfs_last_error(void);
 
