@@ -97,10 +97,29 @@ __device__ __forceinline__ void yz_passes(cx<T>* buf, int cz, int m, int r, cx<T
     });
 }
 
-// Representative x-pencils of the Hermitian pairing P = (l_y, l_z) <-> -P (mod N):
-// rows 1..N/2-1 (all l_z), then rows 0 and N/2 with l_z in 1..N/2-1, then the four
-// self-paired pencils (l_y, l_z in {0, N/2}).  Returns false for self-paired pencils.
-template <int N>
+// Buffer loads: a wave-uniform base in the resource descriptor, the lane's byte offset
+// in a VGPR and a uniform byte offset in an SGPR, so the strided x-pass loads need no
+// per-lane 64-bit address arithmetic.  Offsets beyond the descriptor's range read 0.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t field_rsrc(const cx<T>* base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<cx<T>*>(base), 0, bytes, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> bload(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    } else {
+        return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    }
+}
+
+// Work slots of the x-pass.  The Hermitian pairs P = (l_y, l_z) <-> -P (mod N) by a
+// representative: rows 1..N/2-1 with all l_z, then rows 0 and N/2 with l_z in
+// 1..N/2-1.  The four self-paired pencils (P = -P) follow: with SELF, as two slots that
+// each take (l_y, 0) and (l_y, N/2) for l_y = 0 and l_y = N/2 (N^2/2 slots in all);
+// otherwise one slot each (N^2/2 + 2 slots).  Returns false for a self-paired slot.
+template <int N, bool SELF>
 __device__ __forceinline__ bool pencil_slot(int slot, int& ly, int& lz) {
     constexpr int H = N / 2;
     constexpr int RA = (H - 1) * N;
@@ -116,8 +135,13 @@ __device__ __forceinline__ bool pencil_slot(int slot, int& ly, int& lz) {
         return true;
     }
     const int u = t - 2 * (H - 1);
-    ly = (u >> 1) * H;
-    lz = (u & 1) * H;
+    if constexpr (SELF) {
+        ly = u * H;
+        lz = 0;
+    } else {
+        ly = (u >> 1) * H;
+        lz = (u & 1) * H;
+    }
     return false;
 }
 
@@ -126,20 +150,34 @@ __device__ __forceinline__ bool pencil_slot(int slot, int& ly, int& lz) {
 // over (l_y, l_z)) and keeps only the chunk's x-outputs: the CH strided input
 // sub-sequences are combined with kxt, which carries the x-phase, the split factor
 // e^{2 pi i t c / CH} and the twiddle e^{2 pi i l c / N}.  The y- and z-phases are
-// constant along an x-pencil and multiply its outputs.
+// constant along an x-pencil and multiply its outputs.  With PIPE the loads of the
+// next sub-sequence are issued before the current one is combined.
 //
 // f is real, so f_hat(l_x, -P) = conj(f_hat(-l_x, P)); with the linear x-phase this
 // gives, for every output x-index n, G(-P)[n] = conj(G(P)[n] + delta_P (-1)^n) where
 // delta_P = f_hat(N/2, P) (e^{i theta N/2} - e^{-i theta N/2}) accounts for the DFT
 // index N/2 standing for the mode -N/2 on both sides.  So only one pencil of each pair
 // is transformed; its partner costs a conjugate, one correction and its own y/z phase.
-template <typename T, int N, int CH, int CZ>
+//
+// A self-paired pencil obeys the same relation with itself: its x-output is
+// a - i d (-1)^n / 2 with a real and d = f_hat(N/2, P) 2 sin(theta N/2) (f_hat(N/2, P) is
+// real there).  With SELF two of them, P1 and P2, go through one transform of
+// f_hat(., P1) + i f_hat(., P2), whose output (a1 - b2) + i (b1 + a2) (b = -d (-1)^n / 2)
+// gives both.  That removes a round of the pass when N^2/2 + 2 slots would need one
+// more than N^2/2; only the wavefront holding those two slots loads two pencils.
+template <typename T, int N, int CH, int CZ, bool PIPE>
 __device__ __forceinline__ void field_ifft(const cx<T>* __restrict__ fh, const cx<T>* __restrict__ kxt,
                                            const cx<T>* __restrict__ yzt, T nyq, int c, cx<T>* buf, int cz,
                                            int m, int r, cx<T>* out) {
     using K = GainK<T, N, CH, CZ>;
-    constexpr int SLOTS = N * N / 2 + 2;
-    constexpr int ROUNDS = (SLOTS + K::NT - 1) / K::NT;
+    constexpr int ROUNDS_ALL = (N * N / 2 + 2 + K::NT - 1) / K::NT;
+    constexpr int ROUNDS_SELF = (N * N / 2 + K::NT - 1) / K::NT;
+    constexpr bool SELF = ROUNDS_SELF < ROUNDS_ALL;
+    constexpr int SLOTS = SELF ? N * N / 2 : N * N / 2 + 2;
+    constexpr int ROUNDS = SELF ? ROUNDS_SELF : ROUNDS_ALL;
+    constexpr int ES = int(sizeof(cx<T>));
+    constexpr int RS = N * N * ES;  // bytes between x-planes of the spectrum
+    const __amdgpu_buffer_rsrc_t rs = field_rsrc<T>(fh, N * RS);
     const int tid = threadIdx.x;
     // runtime loops keep the x-pass loads from being hoisted en masse
 #pragma unroll 1
@@ -147,27 +185,74 @@ __device__ __forceinline__ void field_ifft(const cx<T>* __restrict__ fh, const c
         const int slot = tid + k * K::NT;
         if (ROUNDS * K::NT != SLOTS && slot >= SLOTS) break;
         int ly, lz;
-        const bool paired = pencil_slot<N>(slot, ly, lz);
+        const bool paired = pencil_slot<N, SELF>(slot, ly, lz);
         const int P = ly * N + lz;
-        const cx<T>* src = fh + P;
+        const int vo = P * ES;
         cx<T> y[K::NP];
 #pragma unroll
-        for (int l = 0; l < K::NP; ++l) y[l] = src[l * N * N] * kxt[l];
+        for (int l = 0; l < K::NP; ++l) y[l] = cx<T>{T(0), T(0)};
+        if (SELF && __ballot(!paired) != 0) {
+            // f(., P1) + i mk f(., P2) with both loads of an index issued together
+            const int vo2 = paired ? vo : vo + (N / 2) * ES;
+            const T mk = paired ? T(0) : T(1);
 #pragma unroll 1
-        for (int t = 1; t < CH; ++t) {
+            for (int t = 0; t < CH; ++t) {
+                cx<T> a[K::NP], b[K::NP];
 #pragma unroll
-            for (int l = 0; l < K::NP; ++l) {
-                const int jx = l + t * K::NP;
-                cmac(y[l], src[jx * N * N], kxt[jx]);
+                for (int l = 0; l < K::NP; ++l) {
+                    a[l] = bload<T>(rs, vo, (l + t * K::NP) * RS);
+                    b[l] = bload<T>(rs, vo2, (l + t * K::NP) * RS);
+                }
+#pragma unroll
+                for (int l = 0; l < K::NP; ++l)
+                    cmac(y[l], cx<T>{a[l].x - mk * b[l].y, a[l].y + mk * b[l].x}, kxt[l + t * K::NP]);
+            }
+        } else if constexpr (PIPE) {
+            cx<T> nxt[K::NP];
+#pragma unroll
+            for (int l = 0; l < K::NP; ++l) nxt[l] = bload<T>(rs, vo, l * RS);
+#pragma unroll 1
+            for (int t = 0; t < CH; ++t) {
+                cx<T> cur[K::NP];
+#pragma unroll
+                for (int l = 0; l < K::NP; ++l) cur[l] = nxt[l];
+                if (t + 1 < CH) {
+#pragma unroll
+                    for (int l = 0; l < K::NP; ++l) nxt[l] = bload<T>(rs, vo, (l + (t + 1) * K::NP) * RS);
+                }
+#pragma unroll
+                for (int l = 0; l < K::NP; ++l) cmac(y[l], cur[l], kxt[l + t * K::NP]);
+            }
+        } else {
+#pragma unroll 1
+            for (int t = 0; t < CH; ++t) {
+#pragma unroll
+                for (int l = 0; l < K::NP; ++l) {
+                    const int jx = l + t * K::NP;
+                    cmac(y[l], bload<T>(rs, vo, jx * RS), kxt[jx]);
+                }
             }
         }
         fft<K::NP, +1>(y);
+        const cx<T> fn = bload<T>(rs, vo, (N / 2) * RS);
+        if (SELF && !paired) {
+            const T h1 = T(0.5) * nyq * fn.x;
+            const T h2 = T(0.5) * nyq * bload<T>(rs, vo + (N / 2) * ES, (N / 2) * RS).x;
+            const cx<T> c1 = yzt[ly] * yzt[N], c2 = yzt[ly] * yzt[N + N / 2];
+#pragma unroll
+            for (int mm = 0; mm < K::NP; ++mm) {
+                const bool odd = ((CH * mm + c) & 1) != 0;
+                const T e1 = odd ? -h1 : h1, e2 = odd ? -h2 : h2;  // d (-1)^n / 2
+                buf[(mm * N + ly) * K::ROW] = cx<T>{y[mm].x - e2, -e1} * c1;
+                buf[(mm * N + ly) * K::ROW + N / 2] = cx<T>{y[mm].y + e1, -e2} * c2;
+            }
+            continue;
+        }
         const cx<T> cyz = yzt[ly] * yzt[N + lz];
 #pragma unroll
         for (int mm = 0; mm < K::NP; ++mm) buf[(mm * N + ly) * K::ROW + lz] = y[mm] * cyz;
         if (paired) {
             const int ly2 = (N - ly) % N, lz2 = (N - lz) % N;
-            const cx<T> fn = src[(N / 2) * N * N];
             const cx<T> delta = cx<T>{-nyq * fn.y, nyq * fn.x};
             const cx<T> cyz2 = yzt[ly2] * yzt[N + lz2];
 #pragma unroll
@@ -183,7 +268,7 @@ __device__ __forceinline__ void field_ifft(const cx<T>* __restrict__ fh, const c
     __syncthreads();
 }
 
-template <typename T, int N, int CH, int CZ>
+template <typename T, int N, int CH, int CZ, bool PIPE>
 __global__ __launch_bounds__((GainK<T, N, CH, CZ>::NT)) void gain_kernel(GainArgs<T> a) {
     using K = GainK<T, N, CH, CZ>;
     __shared__ cx<T> buf[K::LDS];
@@ -218,9 +303,9 @@ __global__ __launch_bounds__((GainK<T, N, CH, CZ>::NT)) void gain_kernel(GainArg
     for (int d = 0; d < ndir; ++d) {
         const int64_t base = (int64_t(doff + d) * a.nrho + q) * 2;
         cx<T> A[K::NS], B[K::NS];
-        field_ifft<T, N, CH, CZ>(fhi, a.kx + ((base + 0) * CH + c) * N, a.yz + (base + 0) * 2 * N, a.nyq[base],
+        field_ifft<T, N, CH, CZ, PIPE>(fhi, a.kx + ((base + 0) * CH + c) * N, a.yz + (base + 0) * 2 * N, a.nyq[base],
                                  c, buf, cz, m, r, A);
-        field_ifft<T, N, CH, CZ>(fhj, a.kx + ((base + 1) * CH + c) * N, a.yz + (base + 1) * 2 * N,
+        field_ifft<T, N, CH, CZ, PIPE>(fhj, a.kx + ((base + 1) * CH + c) * N, a.yz + (base + 1) * 2 * N,
                                  a.nyq[base + 1], c, buf, cz, m, r, B);
 #pragma unroll
         for (int n = 0; n < K::NS; ++n) S[n] = fma(w, fma(A[n].x, B[n].x, -A[n].y * B[n].y), S[n]);
@@ -370,7 +455,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // ev (optional): 6 events recorded at the stage boundaries (start, after forward FFT,
 // after gain, after radial, after inverse FFTs, after combine).
-template <typename T, int N, int CH, int CZ>
+template <typename T, int N, int CH, int CZ, bool PIPE>
 hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, bool pairs, hipStream_t st,
                      hipEvent_t* ev) {
     auto mark = [&](int k) {
@@ -407,7 +492,7 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
     ga.nb = nb;
     const int64_t ipn = int64_t(ncls) * p.nrho * CH;
     const int64_t groups = ((nb + 7) / 8) * 8 * ipn;
-    gain_kernel<T, N, CH, CZ><<<dim3(unsigned(groups)), dim3(GainK<T, N, CH, CZ>::NT), 0, st>>>(ga);
+    gain_kernel<T, N, CH, CZ, PIPE><<<dim3(unsigned(groups)), dim3(GainK<T, N, CH, CZ>::NT), 0, st>>>(ga);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     mark(2);
 

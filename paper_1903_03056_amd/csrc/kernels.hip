@@ -113,9 +113,10 @@ namespace {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Compiled gain-kernel geometries (CH, CZ) per N and precision; the first is the default.
-constexpr int kTilesF32[][3] = {{16, 1, 1}, {16, 1, 2}, {16, 2, 1}, {24, 3, 2}, {24, 3, 4}, {24, 3, 1},
-                                {32, 4, 1}, {32, 4, 2}, {32, 2, 1}, {48, 6, 2}, {48, 12, 4}, {48, 12, 2}};
+// Compiled gain-kernel geometries (CH, CZ) per N and precision; the first is the default
+// (the fastest measured on MI355X for that N; autotune.py re-measures on the device).
+constexpr int kTilesF32[][3] = {{16, 1, 1}, {16, 2, 1}, {16, 1, 2}, {24, 3, 1}, {24, 3, 2}, {24, 3, 4},
+                                {32, 2, 1}, {32, 4, 1}, {32, 4, 2}, {48, 6, 2}, {48, 12, 4}, {48, 12, 2}};
 constexpr int kTilesF64[][3] = {{16, 1, 1}, {24, 3, 2}, {32, 4, 2}, {48, 12, 4}};
 
 }  // namespace
