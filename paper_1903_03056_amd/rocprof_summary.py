@@ -66,8 +66,8 @@ def main(trace_dir, fetch_dir, write_dir, prefix, command):
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |\n")
     fetch = _counters(fetch_dir, "FETCH_SIZE")
     write = _counters(write_dir, "WRITE_SIZE")
-    fcopy = next(v for k, v in fetch if k == COPY_KERNEL)
-    wcopy = next(v for k, v in write if k == COPY_KERNEL)
+    fcopy = max(v for k, v in fetch if k == COPY_KERNEL)   # the 256 MiB probe copy
+    wcopy = max(v for k, v in write if k == COPY_KERNEL)
     ff, fw = COPY_BYTES / fcopy, COPY_BYTES / wcopy
     with open(prefix + "_hbm_counters.md", "w") as fh:
         fh.write("# HBM traffic per dispatch (rocprofv3 FETCH_SIZE / WRITE_SIZE)\n\nCommands:\n\n```\n"
@@ -99,10 +99,10 @@ if __name__ == "__main__":
     t, f, w, p = sys.argv[1:5]
     cmds = {
         "trace": "rocprofv3 --kernel-trace --stats -d DIR -o trace --output-format csv -- "
-                 "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline",
+                 "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-plain --no-extra",
         "fetch": "rocprofv3 --pmc FETCH_SIZE -d DIR -o fetch --output-format csv -- "
-                 "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-plain --copy-probe",
+                 "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-plain --no-extra --copy-probe",
         "write": "rocprofv3 --pmc WRITE_SIZE -d DIR -o write --output-format csv -- "
-                 "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-plain --copy-probe",
+                 "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-plain --no-extra --copy-probe",
     }
     main(t, f, w, p, cmds)
