@@ -618,8 +618,9 @@ size_t dgfs_plan::ws_per_node(bool pairs) const {
         return best;
     }
     const size_t c = 2 * elem() * n3();
+    const size_t half = 2 * elem() * size_t(N) * N * (N / 2 + 1);  // a Hermitian-half partial
     const int nslots = pairs ? s * s : s;
-    return c * (size_t(s) + classes.size() * size_t(nrho) + 2 * size_t(nslots));
+    return c * (size_t(s) + 2 * size_t(nslots)) + half * classes.size() * size_t(nrho);
 }
 
 extern "C" {

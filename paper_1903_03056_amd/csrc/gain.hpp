@@ -26,7 +26,9 @@ struct GainK {
     static constexpr int NS = N / CZ;
     static constexpr int NTC = NP * N;
     static constexpr int NT = NTC * CZ;
-    static constexpr int PX = (N * N + NT - 1) / NT;   // x-pencils per thread (guarded)
+    static constexpr int KZH = N / 2 + 1;               // stored k_z of a partial (Hermitian half)
+    static constexpr int NPEN = N * KZH;                // stored (k_y, k_z) pencils of a partial
+    static constexpr int PX = (NPEN + NT - 1) / NT;     // stored pencils per thread (guarded)
     static constexpr int ROW = N + 1;                  // padded LDS row (bank spread)
     static constexpr int LDS = NP * N * ROW;
     static_assert(NP * CH == N && NS * CZ == N, "CH and CZ must divide N");
@@ -36,7 +38,7 @@ struct GainK {
 template <typename T>
 struct GainArgs {
     const cx<T>* fhat;  // [nb][s][N^3], DFT / N^3
-    cx<T>* P;           // [nb][ncls][nrho][CH][N/CH][N][N]
+    cx<T>* P;           // [nb][ncls][nrho][CH][N/CH][N][N/2+1]  (k_z <= N/2 of each partial)
     const cx<T>* kx;    // [dirs][nrho][2][CH][N]  x-phase merged with the chunk split
     const cx<T>* yz;    // [dirs][nrho][2][2][N]   y- and z-phases
     const T* nyq;       // [dirs][nrho][2]         2 sin(theta_x N / 2) of the x-phase
@@ -332,18 +334,22 @@ __global__ __launch_bounds__((GainK<T, N, CH, CZ>::NT)) void gain_kernel(GainArg
         for (int j = 0; j < K::NS; ++j) buf[(m * N + CZ * j + cz) * K::ROW + r] = v[j];
         __syncthreads();
     }
-    cx<T>* Pout = a.P + ((int64_t(b) * a.ncls + cl) * a.nrho + q) * N3 + int64_t(c) * (N3 / CH);
+    // The chunk's partial is the DFT of a real array over (x-planes of the chunk, y, z),
+    // so it is Hermitian in (k_xp, k_y, k_z): only k_z <= N/2 is stored, the radial kernel
+    // reads the rest as conjugates of the mirrored entries.
+    constexpr int64_t PCH = int64_t(K::NP) * K::NPEN;  // stored values of one chunk partial
+    cx<T>* Pout = a.P + ((int64_t(b) * a.ncls + cl) * a.nrho + q) * (CH * PCH) + int64_t(c) * PCH;
 #pragma unroll 1
     for (int k = 0; k < K::PX; ++k) {
         const int P = tid + k * K::NT;
-        if (K::PX * K::NT != N * N && P >= N * N) break;
-        const int ky = P / N, kz = P % N;
+        if (K::PX * K::NT != K::NPEN && P >= K::NPEN) break;
+        const int ky = P / K::KZH, kz = P % K::KZH;
         cx<T> v[K::NP];
 #pragma unroll
         for (int mm = 0; mm < K::NP; ++mm) v[mm] = buf[(mm * N + ky) * K::ROW + kz];
         fft<K::NP, -1>(v);
 #pragma unroll
-        for (int kk = 0; kk < K::NP; ++kk) Pout[kk * N * N + P] = v[kk];
+        for (int kk = 0; kk < K::NP; ++kk) Pout[kk * K::NPEN + P] = v[kk];
     }
 }
 
@@ -363,17 +369,24 @@ struct RadialArgs {
     int s, ncls, nrho, nb, nslots, K2;
 };
 
+// One thread per Hermitian pair {k, -k} of the output spectrum: it takes the
+// representative with k_z <= N/2 (the stored half of the partials), forms
+// Q_hat+(k) = sum_terms sum_q w_q F(|k|, rho_q)/N^3 DFT(S_q)(k) and the loss spectrum
+// L(k) = sum_j G-(|k|) f_hat^j(k) for the CH x-modes k_x = k_xp + j N/CH, and writes
+// both at k and their conjugates at -k (S_q and f are real, F and G- are real and even
+// in k).  Pairs with k_z = 0 or N/2 lie wholly in the stored half and are written once.
 template <typename T, int N, int CH>
 __global__ __launch_bounds__(256) void radial_kernel(RadialArgs<T> a) {
     constexpr int NP = N / CH;
-    constexpr int64_t N2 = int64_t(N) * N, N3 = N2 * N, PER = int64_t(NP) * N2;
+    constexpr int KZH = N / 2 + 1;
+    constexpr int64_t N2 = int64_t(N) * N, N3 = N2 * N, PCH = int64_t(NP) * N * KZH;
     const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (t >= int64_t(a.nb) * a.nslots * PER) return;
-    const int e = int(t % PER);
-    const int64_t bs = t / PER;
+    if (t >= int64_t(a.nb) * a.nslots * PCH) return;
+    const int e = int(t % PCH);
+    const int64_t bs = t / PCH;
     const int slot = int(bs % a.nslots);
     const int b = int(bs / a.nslots);
-    const int kz = e % N, ky = (e / N) % N, kxp = e / (N * N);
+    const int kz = e % KZH, ky = (e / KZH) % N, kxp = e / (N * KZH);
     auto sq = [](int k) {
         const int mk = k < N / 2 ? k : k - N;
         return mk * mk;
@@ -383,19 +396,19 @@ __global__ __launch_bounds__(256) void radial_kernel(RadialArgs<T> a) {
 #pragma unroll
     for (int j = 0; j < CH; ++j) k2[j] = sq(kxp + j * NP) + kyz2;
     const int* sd = a.slots + 5 * slot;
-    const int sp = sd[0], g0 = sd[1], ng = sd[2], l0 = sd[3], nl = sd[4];
+    const int g0 = sd[1], ng = sd[2], l0 = sd[3], nl = sd[4];
 
     cx<T> acc[CH];
 #pragma unroll
     for (int j = 0; j < CH; ++j) acc[j] = cx<T>{T(0), T(0)};
     for (int gi = 0; gi < ng; ++gi) {
         const int cl = a.gterms[2 * (g0 + gi)], ft = a.gterms[2 * (g0 + gi) + 1];
-        const cx<T>* Pb = a.P + (int64_t(b) * a.ncls + cl) * a.nrho * N3 + e;
+        const cx<T>* Pb = a.P + (int64_t(b) * a.ncls + cl) * a.nrho * (CH * PCH) + e;
         const T* Ft = a.F + int64_t(ft) * a.nrho * a.K2;
         for (int q = 0; q < a.nrho; ++q) {
             cx<T> pc[CH];
 #pragma unroll
-            for (int c = 0; c < CH; ++c) pc[c] = Pb[int64_t(q) * N3 + c * PER];
+            for (int c = 0; c < CH; ++c) pc[c] = Pb[int64_t(q) * (CH * PCH) + c * PCH];
 #pragma unroll
             for (int j = 0; j < CH; ++j) {
                 const int kx = kxp + j * NP;
@@ -423,13 +436,20 @@ __global__ __launch_bounds__(256) void radial_kernel(RadialArgs<T> a) {
             lac[j].y = fma(gm, v.y, lac[j].y);
         }
     }
-    (void)sp;
-    const int64_t ob = (int64_t(b) * a.nslots + slot) * N3 + ky * N + kz;
+    const int64_t ob = (int64_t(b) * a.nslots + slot) * N3;
+    const bool mirror = kz != 0 && kz != N / 2;
+    const int ky2 = (N - ky) % N, kz2 = (N - kz) % N;
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
         const int kx = kxp + j * NP;
-        a.Gt[ob + kx * N2] = acc[j];
-        a.Lt[ob + kx * N2] = lac[j];
+        const int64_t o = ob + kx * N2 + ky * N + kz;
+        a.Gt[o] = acc[j];
+        a.Lt[o] = lac[j];
+        if (mirror) {
+            const int64_t o2 = ob + ((N - kx) % N) * N2 + ky2 * N + kz2;
+            a.Gt[o2] = cx<T>{acc[j].x, -acc[j].y};
+            a.Lt[o2] = cx<T>{lac[j].x, -lac[j].y};
+        }
     }
 }
 
@@ -468,7 +488,7 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
     cx<T>* fhat = reinterpret_cast<cx<T>*>(w);
     w += align256(sizeof(cx<T>) * nb * p.s * N3);
     cx<T>* P = reinterpret_cast<cx<T>*>(w);
-    w += align256(sizeof(cx<T>) * int64_t(nb) * ncls * p.nrho * N3);
+    w += align256(sizeof(cx<T>) * int64_t(nb) * ncls * p.nrho * (N3 / N) * (N / 2 + 1));
     cx<T>* Gt = reinterpret_cast<cx<T>*>(w);
     cx<T>* Lt = Gt + int64_t(nb) * ss.nslots * N3;  // contiguous with Gt
 
@@ -513,7 +533,7 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
     ra.nb = nb;
     ra.nslots = ss.nslots;
     ra.K2 = p.K2;
-    const int64_t rthreads = int64_t(nb) * ss.nslots * (N3 / CH);
+    const int64_t rthreads = int64_t(nb) * ss.nslots * (N / CH) * N * (N / 2 + 1);
     radial_kernel<T, N, CH><<<dim3(unsigned((rthreads + 255) / 256)), dim3(256), 0, st>>>(ra);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     mark(3);
