@@ -31,6 +31,11 @@ struct GainK {
     static constexpr int PX = (NPEN + NT - 1) / NT;     // stored pencils per thread (guarded)
     static constexpr int ROW = N + 1;                  // padded LDS row (bank spread)
     static constexpr int LDS = NP * N * ROW;
+    // packed form: line-data regions [2][NP][N+1], the correction array [N][ROWC] (in
+    // the main buffer) and the thread groups GC of its transforms (one wavefront each)
+    static constexpr int LINES = 2 * NP * (N + 1);
+    static constexpr int ROWC = N + 2 * NP + 1;
+    static constexpr int GC = (N % 4 == 0 && 256 <= NT) ? 4 : (N % 3 == 0 && 192 <= NT) ? 3 : (128 <= NT) ? 2 : 1;
     static_assert(NP * CH == N && NS * CZ == N, "CH and CZ must divide N");
     static_assert(NTC % 64 == 0, "a CZ group must be whole wavefronts");
 };
@@ -270,10 +275,282 @@ __device__ __forceinline__ void field_ifft(const cx<T>* __restrict__ fh, const c
     __syncthreads();
 }
 
+// ====================================================== packed pair of fields
+// Geometries the packed form supports: at most two x-pass rounds (their plane values
+// stay in registers) and one lane per correction column.
+template <typename T, int N, int CH, int CZ>
+constexpr bool pack_ok() {
+    using K = GainK<T, N, CH, CZ>;
+    constexpr int ra = (N * N / 2 + 2 + K::NT - 1) / K::NT, rs = (N * N / 2 + K::NT - 1) / K::NT;
+    return (rs < ra ? rs : ra) <= 2 && N + 2 * K::NP <= 64 && N * K::ROWC <= K::LDS;
+}
+
+// The chunk x-transform of one pencil P of one field (with SELF in a wavefront holding
+// self-paired slots: of f(., P) + i mk f(., P + N/2), both loads of an index together).
+template <typename T, int N, int CH, bool PIPE>
+__device__ __forceinline__ void x_pencil(__amdgpu_buffer_rsrc_t rs, int vo, int vo2, T mk, bool two,
+                                         const cx<T>* __restrict__ kxt, cx<T>* y) {
+    constexpr int NP = N / CH;
+    constexpr int RS = N * N * int(sizeof(cx<T>));
+#pragma unroll
+    for (int l = 0; l < NP; ++l) y[l] = cx<T>{T(0), T(0)};
+    if (two) {
+#pragma unroll 1
+        for (int t = 0; t < CH; ++t) {
+            cx<T> a[NP], b[NP];
+#pragma unroll
+            for (int l = 0; l < NP; ++l) {
+                a[l] = bload<T>(rs, vo, (l + t * NP) * RS);
+                b[l] = bload<T>(rs, vo2, (l + t * NP) * RS);
+            }
+#pragma unroll
+            for (int l = 0; l < NP; ++l)
+                cmac(y[l], cx<T>{a[l].x - mk * b[l].y, a[l].y + mk * b[l].x}, kxt[l + t * NP]);
+        }
+    } else if constexpr (PIPE) {
+        cx<T> nxt[NP];
+#pragma unroll
+        for (int l = 0; l < NP; ++l) nxt[l] = bload<T>(rs, vo, l * RS);
+#pragma unroll 1
+        for (int t = 0; t < CH; ++t) {
+            cx<T> cur[NP];
+#pragma unroll
+            for (int l = 0; l < NP; ++l) cur[l] = nxt[l];
+            if (t + 1 < CH) {
+#pragma unroll
+                for (int l = 0; l < NP; ++l) nxt[l] = bload<T>(rs, vo, (l + (t + 1) * NP) * RS);
+            }
+#pragma unroll
+            for (int l = 0; l < NP; ++l) cmac(y[l], cur[l], kxt[l + t * NP]);
+        }
+    } else {
+#pragma unroll 1
+        for (int t = 0; t < CH; ++t) {
+#pragma unroll
+            for (int l = 0; l < NP; ++l) cmac(y[l], bload<T>(rs, vo, (l + t * NP) * RS), kxt[l + t * NP]);
+        }
+    }
+    fft<NP, +1>(y);
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> pack_ab(cx<T> a, cx<T> b) { return cx<T>{a.x - b.y, a.y + b.x}; }          // a + i b
+template <typename T>
+__device__ __forceinline__ cx<T> pack_conj(cx<T> a, cx<T> b) { return cx<T>{a.x + b.y, b.x - a.y}; }        // conj(a) + i conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> pack_nconj(cx<T> a, cx<T> b) { return cx<T>{-a.x - b.y, a.y - b.x}; }      // -(conj(a) + i conj(b))
+
+// One direction of a gain class with both shifted fields A = f^i(v + a rho sigma) and
+// B = f^j(v - b rho sigma) carried by one complex transform.
+//
+// After the x-pass of a field, split its mixed-domain data G(x, P) (P = (l_y, l_z)) into
+// the part that is Hermitian in P, whose y/z transform is real, and the anti-Hermitian
+// rest.  For a pencil P with partner -P (see field_ifft for y, delta_P and the sign s_n),
+// with c = cyz(P), c^ = conj(cyz(-P)), c~ = (c + c^)/2:
+//   Herm(P)[n] = y[n] c~ + s_n delta c^ / 2,          Herm(-P) = conj(Herm(P)),
+//   AH(P)[n]   = (c - c^)/2 (y[n] + s_n delta / 2) - s_n delta c~ / 2.
+// The y/z transform of Herm_A + i Herm_B gives a + i b with a = Re A, b = Re B.  The
+// anti-Hermitian part has two pieces, each anti-Hermitian by itself: a plane piece
+// -delta c~ / 2 times s_n (its transform is (-1)^x times one 2-D transform), and a line
+// piece, nonzero only where c != c^, i.e. on the Nyquist lines l_y = N/2 or l_z = N/2
+// (1-D transforms along the other index).  Their transforms are purely imaginary, i alpha,
+// so the pieces of A and B are packed the same way: E = i alpha_A - alpha_B.  Then
+// Re(A B) = a b - alpha_A alpha_B = Re Z Im Z + Re E Im E.
 template <typename T, int N, int CH, int CZ, bool PIPE>
+__device__ __forceinline__ void packed_direction(const cx<T>* __restrict__ fa, const cx<T>* __restrict__ fb,
+                                                 const cx<T>* __restrict__ kxa, const cx<T>* __restrict__ yza,
+                                                 T nyqa, const cx<T>* __restrict__ kxb,
+                                                 const cx<T>* __restrict__ yzb, T nyqb, int c, cx<T>* buf, int cz,
+                                                 int m, int r, T w, T* S) {
+    using K = GainK<T, N, CH, CZ>;
+    constexpr int NP = K::NP, H = N / 2;
+    constexpr int ROUNDS_ALL = (N * N / 2 + 2 + K::NT - 1) / K::NT;
+    constexpr int ROUNDS_SELF = (N * N / 2 + K::NT - 1) / K::NT;
+    constexpr bool SELF = ROUNDS_SELF < ROUNDS_ALL;
+    constexpr int SLOTS = SELF ? N * N / 2 : N * N / 2 + 2;
+    constexpr int ROUNDS = SELF ? ROUNDS_SELF : ROUNDS_ALL;
+    static_assert(ROUNDS <= 2, "the plane values of at most two rounds are kept in registers");
+    static_assert(N + 2 * NP <= 64, "one lane per correction column");
+    static_assert(N * K::ROWC <= K::LDS, "the correction array must fit the main buffer");
+    constexpr int ES = int(sizeof(cx<T>));
+    constexpr int RS = N * N * ES;
+    cx<T>* LY = buf + K::LDS;           // [NP][N+1]: line l_y = N/2, indexed [x][l_z]
+    cx<T>* LZ = LY + NP * (N + 1);      // [NP][N+1]: line l_z = N/2, indexed [x][l_y]
+    const __amdgpu_buffer_rsrc_t rsa = field_rsrc<T>(fa, N * RS), rsb = field_rsrc<T>(fb, N * RS);
+    const int tid = threadIdx.x;
+    cx<T> pl[2][2];  // plane values of the slot's two pencils, per round
+
+#pragma unroll 1
+    for (int k = 0; k < ROUNDS; ++k) {
+        const int slot = tid + k * K::NT;
+        if (ROUNDS * K::NT != SLOTS && slot >= SLOTS) break;
+        int ly, lz;
+        const bool paired = pencil_slot<N, SELF>(slot, ly, lz);
+        const int vo = (ly * N + lz) * ES;
+        const bool two = SELF && __ballot(!paired) != 0;
+        const int vo2 = (SELF && !paired) ? vo + H * ES : vo;
+        const T mk = (SELF && !paired) ? T(1) : T(0);
+        cx<T> ya[NP], yb[NP];
+        x_pencil<T, N, CH, PIPE>(rsa, vo, vo2, mk, two, kxa, ya);
+        x_pencil<T, N, CH, PIPE>(rsb, vo, vo2, mk, two, kxb, yb);
+        const cx<T> fna = bload<T>(rsa, vo, H * RS), fnb = bload<T>(rsb, vo, H * RS);
+        cx<T> p0, p1;
+        if (paired) {
+            const int ly2 = (N - ly) % N, lz2 = (N - lz) % N;
+            const cx<T> da = cx<T>{-nyqa * fna.y, nyqa * fna.x}, db = cx<T>{-nyqb * fnb.y, nyqb * fnb.x};
+            const cx<T> ca = yza[ly] * yza[N + lz], cb = yzb[ly] * yzb[N + lz];
+            const cx<T> c2a = yza[ly2] * yza[N + lz2], c2b = yzb[ly2] * yzb[N + lz2];
+            const cx<T> cha = cx<T>{c2a.x, -c2a.y}, chb = cx<T>{c2b.x, -c2b.y};
+            const cx<T> cta = T(0.5) * (ca + cha), ctb = T(0.5) * (cb + chb);
+            const cx<T> dha = T(0.5) * (da * cha), dhb = T(0.5) * (db * chb);
+#pragma unroll
+            for (int mm = 0; mm < NP; ++mm) {
+                const bool odd = ((CH * mm + c) & 1) != 0;
+                const cx<T> ha = odd ? ya[mm] * cta - dha : ya[mm] * cta + dha;
+                const cx<T> hb = odd ? yb[mm] * ctb - dhb : yb[mm] * ctb + dhb;
+                buf[(mm * N + ly) * K::ROW + lz] = pack_ab(ha, hb);
+                buf[(mm * N + ly2) * K::ROW + lz2] = pack_conj(ha, hb);
+            }
+            if (ly == H || lz == H) {  // line piece (c != c^ only here)
+                const cx<T> ga = T(0.5) * (ca - cha), gb = T(0.5) * (cb - chb);
+                const cx<T> hda = T(0.5) * da, hdb = T(0.5) * db;
+#pragma unroll
+                for (int mm = 0; mm < NP; ++mm) {
+                    const bool odd = ((CH * mm + c) & 1) != 0;
+                    const cx<T> la = ga * (odd ? ya[mm] - hda : ya[mm] + hda);
+                    const cx<T> lb = gb * (odd ? yb[mm] - hdb : yb[mm] + hdb);
+                    if (ly == H) {
+                        LY[mm * (N + 1) + lz] = pack_ab(la, lb);
+                        LY[mm * (N + 1) + lz2] = pack_nconj(la, lb);
+                    } else {
+                        LZ[mm * (N + 1) + ly] = pack_ab(la, lb);
+                        LZ[mm * (N + 1) + ly2] = pack_nconj(la, lb);
+                    }
+                }
+            }
+            const cx<T> pia = T(-0.5) * (da * cta), pib = T(-0.5) * (db * ctb);
+            p0 = pack_ab(pia, pib);
+            p1 = pack_nconj(pia, pib);
+        } else {
+            // self-paired pencils: (ly, lz) alone, or with SELF the pair (ly, 0), (ly, N/2)
+            // from one transform of f(., P1) + i f(., P2) per field
+            const T f2a = SELF ? bload<T>(rsa, vo + H * ES, H * RS).x : T(0);
+            const T f2b = SELF ? bload<T>(rsb, vo + H * ES, H * RS).x : T(0);
+            const T d1a = nyqa * fna.x, d1b = nyqb * fnb.x, d2a = nyqa * f2a, d2b = nyqb * f2b;
+            const int lzs[2] = {SELF ? 0 : lz, H};
+            const T dsa[2] = {d1a, d2a}, dsb[2] = {d1b, d2b};
+#pragma unroll
+            for (int e = 0; e < (SELF ? 2 : 1); ++e) {
+                const int lze = lzs[e];
+                const cx<T> ca = yza[ly] * yza[N + lze], cb = yzb[ly] * yzb[N + lze];
+                const bool line = ly == H || lze == H;
+#pragma unroll
+                for (int mm = 0; mm < NP; ++mm) {
+                    const bool odd = ((CH * mm + c) & 1) != 0;
+                    cx<T> ua = ya[mm], ub = yb[mm];
+                    if (SELF) {  // unscramble: y_k = a_k - i d_k (-1)^n / 2
+                        const T e1a = T(0.5) * (odd ? -d1a : d1a), e2a = T(0.5) * (odd ? -d2a : d2a);
+                        const T e1b = T(0.5) * (odd ? -d1b : d1b), e2b = T(0.5) * (odd ? -d2b : d2b);
+                        ua = e == 0 ? cx<T>{ya[mm].x - e2a, -e1a} : cx<T>{ya[mm].y + e1a, -e2a};
+                        ub = e == 0 ? cx<T>{yb[mm].x - e2b, -e1b} : cx<T>{yb[mm].y + e1b, -e2b};
+                    }
+                    const cx<T> va = ua * ca, vb = ub * cb;
+                    buf[(mm * N + ly) * K::ROW + lze] = cx<T>{va.x, vb.x};
+                    if (line) {
+                        // (c - conj c)/2 (y + s delta / 2) with delta = i d
+                        const T sa = T(0.5) * (odd ? -dsa[e] : dsa[e]), sb = T(0.5) * (odd ? -dsb[e] : dsb[e]);
+                        const cx<T> la = cx<T>{T(0), ca.y} * cx<T>{ua.x, ua.y + sa};
+                        const cx<T> lb = cx<T>{T(0), cb.y} * cx<T>{ub.x, ub.y + sb};
+                        if (ly == H) LY[mm * (N + 1) + lze] = pack_ab(la, lb);
+                        else LZ[mm * (N + 1) + ly] = pack_ab(la, lb);
+                    }
+                }
+                const cx<T> pia = cx<T>{T(0), T(-0.5) * dsa[e] * ca.x}, pib = cx<T>{T(0), T(-0.5) * dsb[e] * cb.x};
+                if (e == 0) p0 = pack_ab(pia, pib);
+                else p1 = pack_ab(pia, pib);
+            }
+        }
+        if (k == 0) {
+            pl[0][0] = p0;
+            pl[0][1] = p1;
+        } else {
+            pl[1][0] = p0;
+            pl[1][1] = p1;
+        }
+    }
+    __syncthreads();
+    cx<T> Z[K::NS];
+    yz_passes<T, N, CH, CZ, +1>(buf, cz, m, r, Z);
+    __syncthreads();
+
+    // the correction array CB[N][ROWC] in the main buffer: the plane at columns 0..N-1
+    // ([l_y][l_z]), then line l_y = N/2 transposed ([l_z][N + x]), then line l_z = N/2
+    // transposed ([l_y][N + NP + x], zero at l_y = N/2)
+    cx<T>* CB = buf;
+#pragma unroll 1
+    for (int k = 0; k < ROUNDS; ++k) {
+        const int slot = tid + k * K::NT;
+        if (ROUNDS * K::NT != SLOTS && slot >= SLOTS) break;
+        int ly, lz;
+        const bool paired = pencil_slot<N, SELF>(slot, ly, lz);
+        const cx<T> v0 = k == 0 ? pl[0][0] : pl[1][0], v1 = k == 0 ? pl[0][1] : pl[1][1];
+        if (paired) {
+            CB[ly * K::ROWC + lz] = v0;
+            CB[((N - ly) % N) * K::ROWC + (N - lz) % N] = v1;
+        } else {
+            CB[ly * K::ROWC + (SELF ? 0 : lz)] = v0;
+            if (SELF) CB[ly * K::ROWC + H] = v1;
+        }
+    }
+    for (int t = tid; t < NP * N; t += K::NT) {
+        const int mm = t / N, l = t % N;
+        CB[l * K::ROWC + N + mm] = LY[mm * (N + 1) + l];
+        CB[l * K::ROWC + N + NP + mm] = l == H ? cx<T>{T(0), T(0)} : LZ[mm * (N + 1) + l];
+    }
+    __syncthreads();
+    const int g = tid / 64, p = tid % 64;
+    {
+        constexpr int NJ = N / K::GC;
+        cx<T> v[NJ];
+        const bool act = g < K::GC && p < N + 2 * NP;
+        if (act) {
+            with_group<K::GC>(g, [&](auto gg) { split_fft<N, K::GC, decltype(gg)::value, +1, K::ROWC>(CB + p, v); });
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) CB[(K::GC * j + g) * K::ROWC + p] = v[j];
+        }
+        __syncthreads();
+        const bool act2 = g < K::GC && p < N;
+        if (act2) {
+            with_group<K::GC>(g, [&](auto gg) { split_fft<N, K::GC, decltype(gg)::value, +1, 1>(CB + p * K::ROWC, v); });
+        }
+        __syncthreads();
+        if (act2) {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) CB[p * K::ROWC + K::GC * j + g] = v[j];
+        }
+        __syncthreads();
+    }
+    // E at the thread's points (x = CH m + c, y = r, z = CZ j + cz)
+    const T sx = ((CH * m + c) & 1) ? T(-1) : T(1), sy = (r & 1) ? T(-1) : T(1);
+    const cx<T> t3 = CB[r * K::ROWC + N + NP + m];
+#pragma unroll
+    for (int j = 0; j < K::NS; ++j) {
+        const int nz = CZ * j + cz;
+        const cx<T> t1 = CB[r * K::ROWC + nz], t2 = CB[nz * K::ROWC + N + m];
+        const T sz = (nz & 1) ? T(-1) : T(1);
+        const T ex = sx * t1.x + sy * t2.x + sz * t3.x, ey = sx * t1.y + sy * t2.y + sz * t3.y;
+        S[j] = fma(w, fma(Z[j].x, Z[j].y, ex * ey), S[j]);
+    }
+    __syncthreads();
+}
+
+template <typename T, int N, int CH, int CZ, bool PIPE, bool PACK>
 __global__ __launch_bounds__((GainK<T, N, CH, CZ>::NT)) void gain_kernel(GainArgs<T> a) {
     using K = GainK<T, N, CH, CZ>;
-    __shared__ cx<T> buf[K::LDS];
+    __shared__ cx<T> buf[K::LDS + ((PACK && pack_ok<T, N, CH, CZ>()) ? K::LINES : 0)];
     // Work items of one node are placed on one XCD (workgroups are dealt to the 8
     // XCDs round-robin), so that node's spectra stay in that XCD's L2.
     const int ipn = a.ncls * a.nrho * CH;
@@ -304,6 +581,12 @@ __global__ __launch_bounds__((GainK<T, N, CH, CZ>::NT)) void gain_kernel(GainArg
 
     for (int d = 0; d < ndir; ++d) {
         const int64_t base = (int64_t(doff + d) * a.nrho + q) * 2;
+        if constexpr (PACK && pack_ok<T, N, CH, CZ>()) {
+            packed_direction<T, N, CH, CZ, PIPE>(fhi, fhj, a.kx + ((base + 0) * CH + c) * N, a.yz + (base + 0) * 2 * N,
+                                                 a.nyq[base], a.kx + ((base + 1) * CH + c) * N,
+                                                 a.yz + (base + 1) * 2 * N, a.nyq[base + 1], c, buf, cz, m, r, w, S);
+            continue;
+        }
         cx<T> A[K::NS], B[K::NS];
         field_ifft<T, N, CH, CZ, PIPE>(fhi, a.kx + ((base + 0) * CH + c) * N, a.yz + (base + 0) * 2 * N, a.nyq[base],
                                  c, buf, cz, m, r, A);
@@ -475,7 +758,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // ev (optional): 6 events recorded at the stage boundaries (start, after forward FFT,
 // after gain, after radial, after inverse FFTs, after combine).
-template <typename T, int N, int CH, int CZ, bool PIPE>
+template <typename T, int N, int CH, int CZ, bool PIPE, bool PACK>
 hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, bool pairs, hipStream_t st,
                      hipEvent_t* ev) {
     auto mark = [&](int k) {
@@ -512,7 +795,7 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
     ga.nb = nb;
     const int64_t ipn = int64_t(ncls) * p.nrho * CH;
     const int64_t groups = ((nb + 7) / 8) * 8 * ipn;
-    gain_kernel<T, N, CH, CZ, PIPE><<<dim3(unsigned(groups)), dim3(GainK<T, N, CH, CZ>::NT), 0, st>>>(ga);
+    gain_kernel<T, N, CH, CZ, PIPE, PACK><<<dim3(unsigned(groups)), dim3(GainK<T, N, CH, CZ>::NT), 0, st>>>(ga);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     mark(2);
 

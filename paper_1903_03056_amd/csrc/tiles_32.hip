@@ -1,5 +1,6 @@
-// Gain-kernel geometries compiled for N = 32: tile = (x-chunks CH, pencil groups CZ), and
-// whether the x-pass double-buffers its loads (chosen per geometry by measurement).
+// Gain-kernel geometries compiled for N = 32: tile = (x-chunks CH, pencil groups CZ),
+// whether the x-pass double-buffers its loads, and whether the two shifted fields share
+// one y/z transform (packed form); both chosen per geometry by measurement.
 #include "gain.hpp"
 
 namespace dgfs {
@@ -9,17 +10,17 @@ hipError_t run_tiles_32(const dgfs_plan& p, const void* f, void* Q, int nb, void
     const int key = p.geo.CH * 100 + p.geo.CZ;
     if (p.precision == DGFS_FP64) {
         switch (key) {
-            case 402: return detail::run_slice<double, 32, 4, 2, false>(
+            case 402: return detail::run_slice<double, 32, 4, 2, false, false>(
                 p, static_cast<const double*>(f), static_cast<double*>(Q), nb, ws, pairs, st, ev);
             default: return hipErrorInvalidValue;
         }
     }
     switch (key) {
-        case 201: return detail::run_slice<float, 32, 2, 1, true>(
+        case 201: return detail::run_slice<float, 32, 2, 1, true, false>(
             p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
-        case 401: return detail::run_slice<float, 32, 4, 1, false>(
+        case 401: return detail::run_slice<float, 32, 4, 1, false, false>(
             p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
-        case 402: return detail::run_slice<float, 32, 4, 2, true>(
+        case 402: return detail::run_slice<float, 32, 4, 2, true, false>(
             p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
         default: return hipErrorInvalidValue;
     }

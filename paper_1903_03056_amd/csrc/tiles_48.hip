@@ -1,5 +1,6 @@
-// Gain-kernel geometries compiled for N = 48: tile = (x-chunks CH, pencil groups CZ), and
-// whether the x-pass double-buffers its loads (chosen per geometry by measurement).
+// Gain-kernel geometries compiled for N = 48: tile = (x-chunks CH, pencil groups CZ),
+// whether the x-pass double-buffers its loads, and whether the two shifted fields share
+// one y/z transform (packed form); both chosen per geometry by measurement.
 #include "gain.hpp"
 
 namespace dgfs {
@@ -9,17 +10,17 @@ hipError_t run_tiles_48(const dgfs_plan& p, const void* f, void* Q, int nb, void
     const int key = p.geo.CH * 100 + p.geo.CZ;
     if (p.precision == DGFS_FP64) {
         switch (key) {
-            case 1204: return detail::run_slice<double, 48, 12, 4, false>(
+            case 1204: return detail::run_slice<double, 48, 12, 4, false, false>(
                 p, static_cast<const double*>(f), static_cast<double*>(Q), nb, ws, pairs, st, ev);
             default: return hipErrorInvalidValue;
         }
     }
     switch (key) {
-        case 602: return detail::run_slice<float, 48, 6, 2, true>(
+        case 602: return detail::run_slice<float, 48, 6, 2, true, true>(
             p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
-        case 1204: return detail::run_slice<float, 48, 12, 4, false>(
+        case 1204: return detail::run_slice<float, 48, 12, 4, false, true>(
             p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
-        case 1202: return detail::run_slice<float, 48, 12, 2, false>(
+        case 1202: return detail::run_slice<float, 48, 12, 2, false, true>(
             p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
         default: return hipErrorInvalidValue;
     }
