@@ -76,7 +76,9 @@ def test_two_species_two_grids(precision, tol, N, M, nrho):
     for b in range(3):
         fb = f[b].astype(np.float32).astype(np.float64) if precision == "f32" else f[b]
         refp = OG.collide_pairs(fb, prob, Ls)
-        assert _rel(Q[b], refp.sum(axis=1)) <= tol
+        rel = _rel(Q[b], refp.sum(axis=1))
+        print(f"node {b}: summed relative L-inf {rel:.3e}", flush=True)
+        assert rel <= tol
         if precision == "f64":
             assert _rel(Qp[b], refp) <= tol
         else:
