@@ -681,9 +681,11 @@ __global__ __launch_bounds__(256) void radial_kernel(RadialArgs<T> a) {
     const int* sd = a.slots + 5 * slot;
     const int g0 = sd[1], ng = sd[2], l0 = sd[3], nl = sd[4];
 
-    cx<T> acc[CH];
+    // the sum over radial points and classes is kept in FP64 (free here: the kernel is
+    // bound by its reads of the partials)
+    cx<double> acc[CH];
 #pragma unroll
-    for (int j = 0; j < CH; ++j) acc[j] = cx<T>{T(0), T(0)};
+    for (int j = 0; j < CH; ++j) acc[j] = cx<double>{0.0, 0.0};
     for (int gi = 0; gi < ng; ++gi) {
         const int cl = a.gterms[2 * (g0 + gi)], ft = a.gterms[2 * (g0 + gi) + 1];
         const cx<T>* Pb = a.P + (int64_t(b) * a.ncls + cl) * a.nrho * (CH * PCH) + e;
@@ -698,9 +700,9 @@ __global__ __launch_bounds__(256) void radial_kernel(RadialArgs<T> a) {
                 cx<T> Sk = pc[0];
 #pragma unroll
                 for (int c = 1; c < CH; ++c) cmac(Sk, a.tw[kx * CH + c], pc[c]);
-                const T fq = Ft[q * a.K2 + k2[j]];
-                acc[j].x = fma(fq, Sk.x, acc[j].x);
-                acc[j].y = fma(fq, Sk.y, acc[j].y);
+                const double fq = double(Ft[q * a.K2 + k2[j]]);
+                acc[j].x = fma(fq, double(Sk.x), acc[j].x);
+                acc[j].y = fma(fq, double(Sk.y), acc[j].y);
             }
         }
     }
@@ -726,11 +728,11 @@ __global__ __launch_bounds__(256) void radial_kernel(RadialArgs<T> a) {
     for (int j = 0; j < CH; ++j) {
         const int kx = kxp + j * NP;
         const int64_t o = ob + kx * N2 + ky * N + kz;
-        a.Gt[o] = acc[j];
+        a.Gt[o] = cx<T>{T(acc[j].x), T(acc[j].y)};
         a.Lt[o] = lac[j];
         if (mirror) {
             const int64_t o2 = ob + ((N - kx) % N) * N2 + ky2 * N + kz2;
-            a.Gt[o2] = cx<T>{acc[j].x, -acc[j].y};
+            a.Gt[o2] = cx<T>{T(acc[j].x), T(-acc[j].y)};
             a.Lt[o2] = cx<T>{lac[j].x, -lac[j].y};
         }
     }
