@@ -17,5 +17,7 @@ Galerkin fast spectral method for the multi-species Boltzmann equation"):
 * ``grids``       species-specific velocity grids: trigonometric interpolation between
                   grids and the pairwise evaluation on the wider grid (the remedy the
                   remark after eq. (domain) in Sec. 4 names and leaves for later).
+* ``stepping``    forward Euler and the second-order SSP Runge-Kutta scheme of Sec. 5
+                  for the spatially homogeneous problem.
 """
-from . import params, quadrature, spectral, moments, bkw, grids  # noqa: F401
+from . import params, quadrature, spectral, moments, bkw, grids, stepping  # noqa: F401
