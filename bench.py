@@ -206,6 +206,31 @@ def species_grid_leg(torch, dev, calls):
     return res, checks
 
 
+def relax_leg(torch, dev, plan, f32, w, steps, dt=0.01):
+    """SSP-RK2 time stepping of the slab workload (two projected operator evaluations
+    per step, all on the device), timed with events around each call."""
+    s = len(w["masses"])
+    f = torch.tensor(f32, device=dev)
+    ws = torch.empty(plan.relax_workspace_bytes(w["batch"]), dtype=torch.uint8, device=dev)
+    plan.relax(f, dt, 1, workspace=ws)      # warm-up, and the state checked against the oracle
+    torch.cuda.synchronize()
+    got = f[0].double().cpu().numpy()
+    st = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    plan.relax(f, dt, steps, workspace=ws)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    res = {"workload": "the slab above advanced by SSP-RK2 (dt = 0.01), two projected collide calls per step",
+           "ms_per_step": round(ms, 3), "steps": steps,
+           "operator_evals_per_s": round(2 * w["batch"] * s * s / (ms * 1e-3), 1)}
+    check = dict(leg="ssprk2_relax", key="node 0 after one step", f=f32[0].astype(np.float64), got=got,
+                 masses=w["masses"], omega=w["omega"], Ls=(w["L"],) * s, N=w["N"], M=w["M"], nrho=w["n_rho"],
+                 dt=dt)
+    return res, [check]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,7 +240,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true",
                     help="leave out the plain per-point FP64 comparison leg (not part of the timed step)")
     ap.add_argument("--no-extra", action="store_true",
-                    help="leave out the uneven-batch, species-grid and measured-ceiling legs")
+                    help="leave out the uneven-batch, species-grid, SSP-RK2 and measured-ceiling legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain device copy of 2 x 256 MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -351,6 +376,9 @@ def main():
         log("species-specific grids")
         extra["heavy_light_species_grids"], c = species_grid_leg(torch, dev, 3)
         checks += c
+        log("SSP-RK2 stepping")
+        extra["ssprk2_relax"], c = relax_leg(torch, dev, plan, f32, w, 10)
+        checks += c
         out["workloads"] = extra
     else:
         checks = []
@@ -372,10 +400,12 @@ def main():
             out["plain_fp64_path"]["max_rel_linf_vs_oracle"] = max(
                 rel_err(Qph[b], outs[b]) for b in range(min(plain_nodes, len(outs))))
         # sampled nodes of the other workloads against the oracle
-        from oracle import grids as OG, spectral as OS
+        from oracle import grids as OG, spectral as OS, stepping as OT
         for c in checks:
             prob = OS.vhs_problem(c["masses"], c["omega"], c["Ls"][0], c["N"], c["M"], c["nrho"])
-            if len(set(c["Ls"])) > 1:
+            if "dt" in c:
+                ref = OT.ssprk2(c["f"], OT.collision_rhs(prob), c["dt"], 1)
+            elif len(set(c["Ls"])) > 1:
                 ref = OG.collide(c["f"], prob, c["Ls"])
             else:
                 ref = OS.collide(c["f"], prob)

@@ -163,6 +163,26 @@ dgfs_status dgfs_conserve(const dgfs_plan* plan, const void* Q_raw, double* Q_ou
 dgfs_status dgfs_conserve_update(const dgfs_plan* plan, const void* Q_raw, void* f, double dt, int64_t batch,
                                  void* stream);
 
+/* Time stepping of the spatially homogeneous problem df/dt = P(Q(f)), with Q the collision
+ * operator of dgfs_collide and P the FP64 conservation projection of dgfs_conserve.
+ * DGFS_EULER:  f <- f + dt P(Q(f)).
+ * DGFS_SSPRK2: the second-order strong-stability-preserving Runge-Kutta scheme that
+ *              Sec. 5 uses in time (and Sec. 6.1 for the Krook-Wu solution):
+ *              f1 = f + dt P(Q(f)),  f <- f/2 + (f1 + dt P(Q(f1)))/2.
+ * Each projected update is computed in FP64 and stored in the plan precision. */
+enum { DGFS_EULER = 0, DGFS_SSPRK2 = 1 };
+
+/* Bytes of device workspace dgfs_relax needs for `batch` nodes in one pass: the stage
+ * states (one for Euler, two for SSP-RK2) plus the collide workspace.  A smaller
+ * workspace (at least the stage states plus one node's collide workspace) makes each
+ * collide run in slices. */
+dgfs_status dgfs_relax_workspace_size(const dgfs_plan* plan, int64_t batch, int32_t scheme, size_t* bytes);
+
+/* Advance f (device [batch][s][N^3], plan precision) in place by `steps` steps of size
+ * dt with `scheme`.  workspace: device memory, 256-byte aligned.  Asynchronous. */
+dgfs_status dgfs_relax(const dgfs_plan* plan, void* f, int64_t batch, double dt, int32_t steps, int32_t scheme,
+                       void* workspace, size_t ws_bytes, void* stream);
+
 /* Host-side view of the precomputed quantities of ordered pair (i, j), for tests:
  *   info[0..5] = a, b, gamma, C_ij, R_ij, number of phase directions used;
  *   rho, w_rho: [n_rho] radial nodes and weights on [0, R_ij];

@@ -21,8 +21,10 @@ EXPORTED = (
     "dgfs_conserve_update", "dgfs_pair_tables", "dgfs_design", "dgfs_interpolation_matrix",
     "dgfs_status_string", "dgfs_last_error", "dgfs_tile_candidates", "dgfs_group_create", "dgfs_group_destroy",
     "dgfs_group_workspace_size", "dgfs_group_collide", "dgfs_group_capture", "dgfs_graph_launch",
-    "dgfs_graph_destroy", "dgfs_probe_valu",
+    "dgfs_graph_destroy", "dgfs_probe_valu", "dgfs_relax_workspace_size", "dgfs_relax",
 )
+
+DGFS_EULER, DGFS_SSPRK2 = 0, 1
 
 
 class PairKernel(ctypes.Structure):
@@ -78,6 +80,8 @@ def load() -> ctypes.CDLL:
     lib.dgfs_design.argtypes = [c_int32, POINTER(c_double)]
     lib.dgfs_interpolation_matrix.argtypes = [c_int32, c_double, c_double, POINTER(c_double)]
     lib.dgfs_probe_valu.argtypes = [c_void_p, c_size_t, c_int32, c_int32, c_void_p, POINTER(c_double)]
+    lib.dgfs_relax_workspace_size.argtypes = [c_void_p, c_int64, c_int32, POINTER(c_size_t)]
+    lib.dgfs_relax.argtypes = [c_void_p, c_void_p, c_int64, c_double, c_int32, c_int32, c_void_p, c_size_t, c_void_p]
     lib.dgfs_tile_candidates.argtypes = [c_int32, c_int32, POINTER(c_int32), c_int32, POINTER(c_int32)]
     lib.dgfs_group_create.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_void_p)]
     lib.dgfs_group_destroy.argtypes = [c_void_p]

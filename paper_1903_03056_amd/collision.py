@@ -232,6 +232,28 @@ class CollisionPlan:
                                              f.shape[0], c_void_p(st.cuda_stream)), "dgfs_conserve_update")
         return f
 
+    def relax_workspace_bytes(self, batch: int, scheme: str = "ssprk2") -> int:
+        n = c_size_t()
+        code = {"euler": _lib.DGFS_EULER, "ssprk2": _lib.DGFS_SSPRK2}[scheme]
+        check(self._lib.dgfs_relax_workspace_size(self._plan, batch, code, ctypes.byref(n)),
+              "dgfs_relax_workspace_size")
+        return n.value
+
+    def relax(self, f, dt: float, steps: int, scheme: str = "ssprk2", workspace=None, stream=None):
+        """Advance f in place by `steps` steps of df/dt = P(Q(f)) (dgfs_relax); scheme is
+        "euler" or "ssprk2" (the second-order SSP Runge-Kutta scheme)."""
+        import torch
+        self._check_f(f)
+        code = {"euler": _lib.DGFS_EULER, "ssprk2": _lib.DGFS_SSPRK2}[scheme]
+        if workspace is None:
+            workspace = torch.empty(self.relax_workspace_bytes(max(f.shape[0], 1), scheme), dtype=torch.uint8,
+                                    device=f.device)
+        st = stream if stream is not None else torch.cuda.current_stream(f.device)
+        check(self._lib.dgfs_relax(self._plan, c_void_p(f.data_ptr()), f.shape[0], float(dt), int(steps), code,
+                                   c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
+                                   c_void_p(st.cuda_stream)), "dgfs_relax")
+        return f
+
     def conserve(self, Q, out=None, stream=None):
         """FP64 conservation projection of a raw collision result (same layout as f)."""
         import torch

@@ -803,6 +803,61 @@ dgfs_status dgfs_conserve_update(const dgfs_plan* plan, const void* Q_raw, void*
     return DGFS_OK;
 }
 
+// ------------------------------------------------------------------ stepping
+static size_t state_bytes(const dgfs_plan* plan, int64_t batch) {
+    return (size_t(batch) * plan->s * plan->n3() * plan->elem() + 255) & ~size_t(255);
+}
+
+dgfs_status dgfs_relax_workspace_size(const dgfs_plan* plan, int64_t batch, int32_t scheme, size_t* bytes) {
+    if (!plan || !bytes) return fail(DGFS_EINVAL, "plan and bytes are required");
+    if (batch < 1) return fail(DGFS_EINVAL, "batch must be >= 1");
+    if (scheme != DGFS_EULER && scheme != DGFS_SSPRK2) return fail(DGFS_EINVAL, "unknown scheme");
+    *bytes = state_bytes(plan, batch) * (scheme == DGFS_SSPRK2 ? 2 : 1) + plan->ws_per_node(false) * size_t(batch) +
+             plan->ws_slack();
+    return DGFS_OK;
+}
+
+dgfs_status dgfs_relax(const dgfs_plan* plan, void* f, int64_t batch, double dt, int32_t steps, int32_t scheme,
+                       void* workspace, size_t ws_bytes, void* stream) {
+    if (!plan) return fail(DGFS_EINVAL, "plan is NULL");
+    if (batch < 0 || steps < 0) return fail(DGFS_EINVAL, "batch and steps must be >= 0");
+    if (scheme != DGFS_EULER && scheme != DGFS_SSPRK2) return fail(DGFS_EINVAL, "unknown scheme");
+    if (!std::isfinite(dt)) return fail(DGFS_EINVAL, "dt must be finite");
+    if (batch == 0 || steps == 0) return DGFS_OK;
+    if (!f || !workspace) return fail(DGFS_EINVAL, "f and workspace are required");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(DGFS_EINVAL, "workspace must be 256-byte aligned");
+    const size_t sb = state_bytes(plan, batch);
+    const size_t fixed = sb * (scheme == DGFS_SSPRK2 ? 2 : 1);
+    if (ws_bytes < fixed + plan->ws_per_node(false) + plan->ws_slack())
+        return fail(DGFS_ENOMEM, "workspace smaller than the stage states plus one node");
+    char* w = static_cast<char*>(workspace);
+    void* Q = w;
+    void* f1 = scheme == DGFS_SSPRK2 ? w + sb : nullptr;
+    void* cw = w + fixed;
+    const size_t cwb = ws_bytes - fixed;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n = batch * plan->s * int64_t(plan->n3());
+    auto dev = [&](hipError_t e) {
+        return e == hipSuccess ? DGFS_OK : fail(DGFS_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    };
+    dgfs_status rc = DGFS_OK;
+    for (int32_t k = 0; k < steps && rc == DGFS_OK; ++k) {
+        if (scheme == DGFS_EULER) {
+            if ((rc = collide_impl(plan, f, Q, batch, cw, cwb, stream, false, nullptr)) != DGFS_OK) break;
+            rc = dev(dgfs::launch_conserve(*plan, Q, nullptr, f, dt, batch, st));
+            continue;
+        }
+        // f1 = f + dt L(f);  f1 <- f1 + dt L(f1);  f <- (f + f1) / 2
+        if ((rc = dev(hipMemcpyAsync(f1, f, size_t(n) * plan->elem(), hipMemcpyDeviceToDevice, st))) != DGFS_OK) break;
+        if ((rc = collide_impl(plan, f, Q, batch, cw, cwb, stream, false, nullptr)) != DGFS_OK) break;
+        if ((rc = dev(dgfs::launch_conserve(*plan, Q, nullptr, f1, dt, batch, st))) != DGFS_OK) break;
+        if ((rc = collide_impl(plan, f1, Q, batch, cw, cwb, stream, false, nullptr)) != DGFS_OK) break;
+        if ((rc = dev(dgfs::launch_conserve(*plan, Q, nullptr, f1, dt, batch, st))) != DGFS_OK) break;
+        rc = dev(dgfs::launch_axpby(*plan, f, f1, f, 0.5, 0.5, n, st));
+    }
+    return rc;
+}
+
 dgfs_status dgfs_tile_candidates(int32_t N, int32_t precision, int32_t* pairs, int32_t max_pairs, int32_t* count) {
     if (!count) return fail(DGFS_EINVAL, "count is required");
     dgfs::GainGeometry cand[16];

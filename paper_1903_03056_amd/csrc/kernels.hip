@@ -108,6 +108,14 @@ __global__ __launch_bounds__(1024) void conserve_kernel(const TIN* Q, double* ou
     }
 }
 
+// ======================================================= elementwise (stepping)
+// out = a x + b y over n values (x, y, out may coincide elementwise).
+template <typename T>
+__global__ __launch_bounds__(256) void axpby_kernel(const T* x, const T* y, T* out, T a, T b, int64_t n) {
+    const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (t < n) out[t] = a * x[t] + b * y[t];
+}
+
 // ================================================================== launches
 namespace {
 
@@ -169,6 +177,19 @@ hipError_t launch_conserve(const dgfs_plan& p, const void* Q, double* out, void*
             conserve_kernel<float, false><<<grid, block, 0, st>>>(static_cast<const float*>(Q), out, nullptr, 0.0,
                                                                   minv, mass, Ls, p.s, p.N);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby(const dgfs_plan& p, const void* x, const void* y, void* out, double a, double b, int64_t n,
+                        hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const dim3 grid(static_cast<unsigned>((n + 255) / 256)), block(256);
+    if (p.precision == DGFS_FP64)
+        axpby_kernel<double><<<grid, block, 0, st>>>(static_cast<const double*>(x), static_cast<const double*>(y),
+                                                      static_cast<double*>(out), a, b, n);
+    else
+        axpby_kernel<float><<<grid, block, 0, st>>>(static_cast<const float*>(x), static_cast<const float*>(y),
+                                                     static_cast<float*>(out), float(a), float(b), n);
     return hipGetLastError();
 }
 

@@ -108,6 +108,9 @@ hipError_t launch_conserve(const dgfs_plan& p, const void* Q, double* out, void*
 // tmp: 2 nb N^3 values of scratch.
 hipError_t launch_move(const dgfs_plan& p, const void* in, int64_t in_stride, void* out, int64_t out_stride,
                        const void* Tm, int64_t nb, bool accumulate, void* tmp, hipStream_t stream);
+// out = a x + b y over n values of the plan precision.
+hipError_t launch_axpby(const dgfs_plan& p, const void* x, const void* y, void* out, double a, double b, int64_t n,
+                        hipStream_t stream);
 // Plain per-point FP64 path (plain.hip).
 size_t plain_ws_bytes(const dgfs_plan& p);
 hipError_t launch_collide_plain(const dgfs_plan& p, const double* f, double* Q, int64_t nb, void* ws,
