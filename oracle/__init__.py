@@ -12,6 +12,8 @@ Galerkin fast spectral method for the multi-species Boltzmann equation"):
 * ``quadrature``  Gauss-Legendre radial rule, spherical designs (Sec. 4).
 * ``spectral``    Fourier coefficients, kernel mode F, loss weight G^-, the direct
                   O(N^6) spectral sum, the fast sum, and the exact-sphere variant.
+* ``vss``         the sigma-dependent kernel mode of the VSS kernels, alpha in (1, 2]
+                  (Sec. 2 eq. VSS, Sec. 4 below eq. GG).
 * ``moments``     moments, the Maxwellian, the FP64 conservation projection.
 * ``bkw``         the Krook-Wu exact solution and its time derivative (Sec. 6.1).
 * ``grids``       species-specific velocity grids: trigonometric interpolation between
@@ -20,4 +22,4 @@ Galerkin fast spectral method for the multi-species Boltzmann equation"):
 * ``stepping``    forward Euler and the second-order SSP Runge-Kutta scheme of Sec. 5
                   for the spatially homogeneous problem.
 """
-from . import params, quadrature, spectral, moments, bkw, grids, stepping  # noqa: F401
+from . import params, quadrature, vss, spectral, moments, bkw, grids, stepping  # noqa: F401

@@ -24,6 +24,8 @@ then, with int_{S^2} e^{-i z k.g_hat} dg_hat = 4 pi sin(z|k|)/(z|k|),
     F(k, rho)  = 4 pi C rho^{gamma+2} sinc(pi a rho |k| / L)       (independent of sigma),
     G-(m)      = 16 pi^2 C int_0^R rho^{gamma+2} sinc(pi rho |m| / L) d rho,
 where sinc(x) = sin(x)/x.  C is the pair prefactor, so Q^{ij} here already carries it.
+For the VSS kernels (1 < alpha <= 2) F depends on sigma and is complex; it comes from
+``vss.kernel_mode`` and G- carries the factor 2^{alpha-1}/alpha (see that module).
 
 Three evaluations of the same discretised operator are provided:
 * ``collide_pair_direct``: eq. (sum) as an explicit O(N^6) double loop with explicit
@@ -44,6 +46,7 @@ import scipy.special
 
 from . import params as P
 from . import quadrature as Qd
+from . import vss as V
 
 # FFT worker threads: the host's CPU share (OMP_NUM_THREADS when set).
 WORKERS = max(1, min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS") or (os.cpu_count() or 1))))
@@ -93,8 +96,11 @@ def kernel_mode_F(kabs, rho: float, a: float, gamma: float, C: float, L: float):
     return 4.0 * np.pi * C * rho ** (gamma + 2.0) * sinc(np.pi * a * rho * np.asarray(kabs) / L)
 
 
-def loss_weight(kabs, R: float, gamma: float, C: float, L: float, tol: float = 1e-14) -> np.ndarray:
-    """G-(m) = 16 pi^2 C int_0^R rho^{gamma+2} sinc(pi rho |m| / L) d rho.
+def loss_weight(kabs, R: float, gamma: float, C: float, L: float, tol: float = 1e-14,
+                alpha: float = 1.0) -> np.ndarray:
+    """G-(m) = 16 pi^2 C int_0^R rho^{gamma+2} sinc(pi rho |m| / L) d rho, times
+    2^{alpha-1}/alpha for a VSS kernel (the sigma integral of (1 + cos chi)^{alpha-1}
+    over 4 pi).
 
     The radial integral uses Gauss-Jacobi quadrature for the weight rho^{gamma+2}
     (so the non-smooth factor rho^{gamma+2} is integrated exactly), doubling the
@@ -121,7 +127,8 @@ def loss_weight(kabs, R: float, gamma: float, C: float, L: float, tol: float = 1
         if n >= 1024:
             raise RuntimeError("loss-weight quadrature did not converge")
         prev = cur
-    return (16.0 * np.pi ** 2 * C * cur)[inv].reshape(kabs.shape)
+    sigma_factor = V.sphere_weight_integral(alpha) / (4.0 * np.pi)
+    return (16.0 * np.pi ** 2 * C * sigma_factor * cur)[inv].reshape(kabs.shape)
 
 
 # ------------------------------------------------------------------ pair set-up
@@ -138,19 +145,30 @@ class Pair:
     wrho: np.ndarray
     sigma: np.ndarray    # (M, 3) sphere points
     wsigma: np.ndarray   # (M,)
+    alpha: float = 1.0   # scattering parameter; > 1 for VSS
+
+    def kernel_mode(self, kvec, q: int, p: int):
+        """F(k, rho_q, sigma_p) at signed mode vectors kvec [..., 3]."""
+        if self.alpha == 1.0:
+            return kernel_mode_F(np.linalg.norm(kvec, axis=-1), self.rho[q], self.a, self.gamma, self.C, self.L)
+        return V.kernel_mode(kvec, self.rho[q], self.sigma[p], self.a, self.gamma, self.alpha, self.C, self.L)
+
+    def loss(self, kabs):
+        return loss_weight(kabs, self.R, self.gamma, self.C, self.L, alpha=self.alpha)
 
 
 def make_pair(mi: float, mj: float, omega: float, C: float, L: float, nrho: int,
               sigma: np.ndarray, wsigma: np.ndarray, R: float | None = None,
               alpha: float = 1.0) -> Pair:
-    if alpha != 1.0:
-        raise NotImplementedError("the oracle covers the VHS family (alpha = 1)")
+    if not 1.0 <= alpha <= 2.0:
+        raise ValueError("alpha must be in [1, 2]")
     a, b = P.pair_ab(mi, mj)
     if R is None:
         R = P.truncation_radius(L, mi, mj)
     rho, wrho = Qd.gauss_legendre(R, nrho)
     return Pair(a=a, b=b, gamma=P.gamma_exponent(omega), C=C, R=R, L=L, rho=rho, wrho=wrho,
-                sigma=np.asarray(sigma, dtype=np.float64), wsigma=np.asarray(wsigma, dtype=np.float64))
+                sigma=np.asarray(sigma, dtype=np.float64), wsigma=np.asarray(wsigma, dtype=np.float64),
+                alpha=float(alpha))
 
 
 # ------------------------------------------------------------------ direct sum
@@ -173,7 +191,7 @@ def collide_pair_direct(fi: np.ndarray, fj: np.ndarray, pr: Pair, exact_sphere: 
     idx = np.stack(np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij"), -1).reshape(-1, 3)
     modes = ks[idx]                                         # (N^3, 3) signed modes
     mabs = np.linalg.norm(modes, axis=1)
-    Gminus = loss_weight(mabs, pr.R, pr.gamma, pr.C, L)     # G-(m) for every m
+    Gminus = pr.loss(mabs)                                  # G-(m) for every m
     Qhat = np.zeros(N ** 3, dtype=np.complex128)
     rho, wrho = pr.rho, pr.wrho
     for li in range(N ** 3):
@@ -183,12 +201,16 @@ def collide_pair_direct(fi: np.ndarray, fj: np.ndarray, pr: Pair, exact_sphere: 
         d = pr.a * modes[li][None, :] - pr.b * modes                      # a l - b m, (N^3, 3)
         Gplus = np.zeros(N ** 3, dtype=np.complex128)
         for q in range(len(rho)):
-            Fq = kernel_mode_F(kabs, rho[q], pr.a, pr.gamma, pr.C, L)
             if exact_sphere:
+                if pr.alpha != 1.0:
+                    raise ValueError("the closed-form sigma integral holds for alpha = 1 only")
+                Fq = kernel_mode_F(kabs, rho[q], pr.a, pr.gamma, pr.C, L)
                 ang = 4.0 * np.pi * sinc(np.pi * rho[q] * np.linalg.norm(d, axis=1) / L)
-            else:
-                ang = np.exp(1j * np.pi * rho[q] * (d @ pr.sigma.T) / L) @ pr.wsigma
-            Gplus += wrho[q] * Fq * ang
+                Gplus += wrho[q] * Fq * ang
+                continue
+            for p in range(len(pr.wsigma)):
+                Fqp = pr.kernel_mode(kmode, q, p)
+                Gplus += wrho[q] * pr.wsigma[p] * Fqp * np.exp(1j * np.pi * rho[q] * (d @ pr.sigma[p]) / L)
         contrib = (Gplus - Gminus) * fhi[li] * fhj
         np.add.at(Qhat, kflat, contrib)
     return synthesize(Qhat.reshape(N, N, N), L).real
@@ -234,17 +256,18 @@ def collide_pair_fast(fi: np.ndarray, fj: np.ndarray, pr: Pair) -> np.ndarray:
     fhj = _coefficients_fft(fj)
     KX, KY, KZ = mode_grids(N)
     kabs = np.sqrt(KX ** 2 + KY ** 2 + KZ ** 2)
+    kvec = np.stack([KX, KY, KZ], axis=-1)
     Qplus = np.zeros((N, N, N), dtype=np.complex128)
     for q in range(len(pr.rho)):
         rho = pr.rho[q]
-        Fq = kernel_mode_F(kabs, rho, pr.a, pr.gamma, pr.C, L)
         for p in range(len(pr.wsigma)):
+            Fqp = pr.kernel_mode(kvec, q, p)
             s = pr.sigma[p]
             ksig = KX * s[0] + KY * s[1] + KZ * s[2]
             X = np.exp(1j * np.pi * rho * pr.a * ksig / L) * fhi
             Y = np.exp(-1j * np.pi * rho * pr.b * ksig / L) * fhj
-            Qplus += pr.wrho[q] * pr.wsigma[p] * Fq * circular_convolution(X, Y)
-    Gm = loss_weight(kabs, pr.R, pr.gamma, pr.C, L)
+            Qplus += pr.wrho[q] * pr.wsigma[p] * Fqp * circular_convolution(X, Y)
+    Gm = pr.loss(kabs)
     Qminus = circular_convolution(fhi, Gm * fhj)
     return _synthesize_fft(Qplus - Qminus).real
 
@@ -257,7 +280,7 @@ def collide_pair_fast_parts(fi: np.ndarray, fj: np.ndarray, pr: Pair):
     fhj = _coefficients_fft(fj)
     KX, KY, KZ = mode_grids(N)
     kabs = np.sqrt(KX ** 2 + KY ** 2 + KZ ** 2)
-    Gm = loss_weight(kabs, pr.R, pr.gamma, pr.C, L)
+    Gm = pr.loss(kabs)
     Qminus = _synthesize_fft(circular_convolution(fhi, Gm * fhj)).real
     Qfull = collide_pair_fast(fi, fj, pr)
     return Qfull + Qminus, Qminus
