@@ -58,9 +58,11 @@ typedef enum {
 
 enum { DGFS_FP32 = 0, DGFS_FP64 = 1 };
 
-/* Collision kernel of one ordered pair: B_ij = prefactor * |g|^{2(1-omega)}
- * (VHS, Sec. 2 eq. VSS with alpha = 1).  omega in [0.5, 1]; alpha must be 1
- * (the VSS case alpha > 1 returns DGFS_EUNSUPPORTED).  prefactor > 0. */
+/* Collision kernel of one ordered pair (Sec. 2 eq. VSS, dimensionless form NVSS):
+ * B_ij = prefactor * |g|^{2(1-omega)} * (1 + cos chi)^{alpha-1}, cos chi = sigma . g_hat.
+ * omega in [0.5, 1]; alpha in [1, 2] (1: VHS/HS/Maxwell, > 1: variable soft spheres,
+ * whose kernel mode depends on sigma: the plan then keeps one complex table per
+ * direction and radial point); prefactor > 0.  The kernel must be symmetric in (i, j). */
 typedef struct {
     double omega;
     double alpha;
@@ -141,7 +143,8 @@ dgfs_status dgfs_collide_pairs(const dgfs_plan* plan, const void* f, void* Q, in
  * pair, radial point and all M directions: phase multiply, inverse 3-D FFTs, product
  * accumulation; per radial point a forward FFT and the radial weighting; then the loss
  * convolution), without the class sharing of the antipodal designs.  Needs an FP64 plan
- * (DGFS_EUNSUPPORTED otherwise).  f, Q: device doubles [batch][s][N^3];
+ * on one common grid with alpha = 1 for every pair (DGFS_EUNSUPPORTED otherwise).
+ * f, Q: device doubles [batch][s][N^3];
  * ws_bytes >= dgfs_workspace_size(plan, 1). */
 dgfs_status dgfs_collide_plain(const dgfs_plan* plan, const double* f, double* Q, int64_t batch,
                                void* workspace, size_t ws_bytes, void* stream);
@@ -190,6 +193,14 @@ dgfs_status dgfs_relax(const dgfs_plan* plan, void* f, int64_t batch, double dt,
  * Any output pointer may be NULL.  No device is touched. */
 dgfs_status dgfs_pair_tables(const dgfs_problem* problem, int32_t i, int32_t j, double* info,
                              double* rho, double* w_rho, double* loss);
+
+/* Host evaluation of the kernel mode of Sec. 4 (below eq. GG) for a VSS kernel, for tests:
+ * F(k, rho, sigma) = rho^2 int_{S^2} C rho^gamma (1 + sigma.g_hat)^{alpha-1}
+ *                    e^{-i pi rho a k.g_hat / L} dg_hat,
+ * k: [3] mode vector, sigma: [3] unit vector, F: [2] real and imaginary part.  Uses the
+ * same series as plan creation.  No device is touched. */
+dgfs_status dgfs_kernel_mode(double alpha, double gamma, double C, double a, double L, double rho, const double* k,
+                             const double* sigma, double* F);
 
 /* Gain-kernel geometries compiled for (N, precision), as pairs (ch, cz) in
  * pairs[2*k], pairs[2*k+1], k < *count <= max_pairs; the first is the default. */

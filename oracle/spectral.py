@@ -261,7 +261,10 @@ def collide_pair_fast(fi: np.ndarray, fj: np.ndarray, pr: Pair) -> np.ndarray:
     for q in range(len(pr.rho)):
         rho = pr.rho[q]
         for p in range(len(pr.wsigma)):
-            Fqp = pr.kernel_mode(kvec, q, p)
+            if pr.alpha == 1.0:
+                Fqp = pr.kernel_mode(kvec, q, p)
+            else:
+                Fqp = V.kernel_mode_grid(N, rho, pr.sigma[p], pr.a, pr.gamma, pr.alpha, pr.C, L)
             s = pr.sigma[p]
             ksig = KX * s[0] + KY * s[1] + KZ * s[2]
             X = np.exp(1j * np.pi * rho * pr.a * ksig / L) * fhi

@@ -26,6 +26,8 @@ so G-(m) for alpha > 1 is the alpha = 1 weight times 2^{alpha-1} / alpha.
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 import scipy.special
 
@@ -74,3 +76,22 @@ def kernel_mode(kvec, rho: float, sigma, a: float, gamma: float, alpha: float, C
         sel = bins == bn
         out[sel] = _integral(z[sel], mu[sel], alpha, nodes(8.0 * (bn + 1)))
     return (2.0 * np.pi * C * rho ** (gamma + 2.0) * out).reshape(shape)
+
+
+@functools.lru_cache(maxsize=800)
+def _grid_cached(N: int, rho: float, sigma: tuple, a: float, gamma: float, alpha: float, C: float,
+                 L: float) -> np.ndarray:
+    j = np.arange(N)
+    m = np.where(j < N // 2, j, j - N).astype(np.float64)
+    kvec = np.stack(np.meshgrid(m, m, m, indexing="ij"), axis=-1)
+    F = kernel_mode(kvec, rho, np.array(sigma), a, gamma, alpha, C, L)
+    F.flags.writeable = False
+    return F
+
+
+def kernel_mode_grid(N: int, rho: float, sigma, a: float, gamma: float, alpha: float, C: float,
+                     L: float) -> np.ndarray:
+    """F at every mode of the N^3 grid (DFT index order), remembered across calls: the
+    same pair and quadrature point recur for every spatial point and time step."""
+    return _grid_cached(int(N), float(rho), tuple(float(x) for x in sigma), float(a), float(gamma), float(alpha),
+                        float(C), float(L))

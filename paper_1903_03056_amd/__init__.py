@@ -12,6 +12,7 @@ from .collision import (  # noqa: F401
     check_problem,
     design,
     interpolation_matrix,
+    kernel_mode,
     pair_tables,
     vhs_kernel,
     vhs_prefactor,

@@ -18,7 +18,7 @@ DGFS_FP32, DGFS_FP64 = 0, 1
 EXPORTED = (
     "dgfs_check_problem", "dgfs_plan_create", "dgfs_plan_destroy", "dgfs_workspace_size",
     "dgfs_collide", "dgfs_collide_timed", "dgfs_collide_pairs", "dgfs_collide_plain", "dgfs_conserve",
-    "dgfs_conserve_update", "dgfs_pair_tables", "dgfs_design", "dgfs_interpolation_matrix",
+    "dgfs_conserve_update", "dgfs_pair_tables", "dgfs_design", "dgfs_interpolation_matrix", "dgfs_kernel_mode",
     "dgfs_status_string", "dgfs_last_error", "dgfs_tile_candidates", "dgfs_group_create", "dgfs_group_destroy",
     "dgfs_group_workspace_size", "dgfs_group_collide", "dgfs_group_capture", "dgfs_graph_launch",
     "dgfs_graph_destroy", "dgfs_probe_valu", "dgfs_relax_workspace_size", "dgfs_relax",
@@ -79,6 +79,8 @@ def load() -> ctypes.CDLL:
                                      POINTER(c_double), POINTER(c_double)]
     lib.dgfs_design.argtypes = [c_int32, POINTER(c_double)]
     lib.dgfs_interpolation_matrix.argtypes = [c_int32, c_double, c_double, POINTER(c_double)]
+    lib.dgfs_kernel_mode.argtypes = [c_double, c_double, c_double, c_double, c_double, c_double, POINTER(c_double),
+                                     POINTER(c_double), POINTER(c_double)]
     lib.dgfs_probe_valu.argtypes = [c_void_p, c_size_t, c_int32, c_int32, c_void_p, POINTER(c_double)]
     lib.dgfs_relax_workspace_size.argtypes = [c_void_p, c_int64, c_int32, POINTER(c_size_t)]
     lib.dgfs_relax.argtypes = [c_void_p, c_void_p, c_int64, c_double, c_int32, c_int32, c_void_p, c_size_t, c_void_p]

@@ -84,6 +84,17 @@ def interpolation_matrix(N: int, L_from: float, L_to: float) -> np.ndarray:
     return np.array(out[:]).reshape(N, N)
 
 
+def kernel_mode(alpha: float, gamma: float, C: float, a: float, L: float, rho: float, k, sigma) -> complex:
+    """The library's host evaluation of the (VSS) kernel mode F(k, rho, sigma)."""
+    lib = load()
+    kk = (c_double * 3)(*[float(x) for x in k])
+    sg = (c_double * 3)(*[float(x) for x in sigma])
+    out = (c_double * 2)()
+    check(lib.dgfs_kernel_mode(float(alpha), float(gamma), float(C), float(a), float(L), float(rho), kk, sg, out),
+          "dgfs_kernel_mode")
+    return complex(out[0], out[1])
+
+
 def pair_tables(masses, L, N, M, n_rho, kernel, i, j, precision="f32", L_species=None) -> dict:
     """Host-side precomputed quantities of ordered pair (i, j)."""
     lib = load()
@@ -105,13 +116,13 @@ class CollisionPlan:
     prefactor of eqs. (Kn)/(NVSS) with Kn0 = ``kn0``."""
 
     def __init__(self, masses, N: int, L, M: int, n_rho: int, omega: float | None = None,
-                 kernel=None, precision="f32", kn0: float = 1.0, tile=None):
+                 kernel=None, precision="f32", kn0: float = 1.0, tile=None, alpha: float = 1.0):
         import torch  # noqa: F401  (initialises the HIP runtime the library shares)
 
         if kernel is None:
             if omega is None:
                 raise ValueError("give omega or kernel")
-            kernel = vhs_kernel(masses, omega, 1.0, kn0)
+            kernel = vhs_kernel(masses, omega, alpha, kn0)
         self.masses = tuple(float(m) for m in masses)
         # L: one half-width for every species, or one per species (species-specific grids)
         Ls = np.broadcast_to(np.asarray(L, dtype=np.float64), (len(masses),))

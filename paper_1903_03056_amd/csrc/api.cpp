@@ -56,8 +56,6 @@ dgfs_status check(const dgfs_problem* p) {
             if (k.omega != t.omega || k.alpha != t.alpha || k.prefactor != t.prefactor)
                 return fail(DGFS_EINVAL, "kernel must be symmetric in (i, j)");
         }
-    for (int i = 0; i < p->s * p->s; ++i)
-        if (p->kernel[i].alpha != 1.0) return fail(DGFS_EUNSUPPORTED, "VSS kernels (alpha > 1) are not implemented");
     if (!n_supported(p->N)) return fail(DGFS_EUNSUPPORTED, "N must be 16, 24, 32 or 48");
     dgfs::GainGeometry g;
     if (!dgfs::gain_geometry(p->N, p->precision, &g))
@@ -85,6 +83,7 @@ dgfs::PairParams pair_params(const dgfs_problem* p, int i, int j) {
     pp.b = mi / (mi + mj);
     pp.gamma = 2.0 * (1.0 - p->kernel[i * p->s + j].omega);
     pp.C = p->kernel[i * p->s + j].prefactor;
+    pp.alpha = p->kernel[i * p->s + j].alpha;
     pp.R = dgfs::pre::truncation_radius(pair_box(p, i, j), mi, mj);
     dgfs::pre::gauss_legendre(p->n_rho, pp.R, pp.rho, pp.wrho);
     return pp;
@@ -190,6 +189,67 @@ std::vector<double> conserve_pack(const std::vector<double>& mass, const std::ve
 }
 
 // Build every host table and lay it out in one byte blob for the device.
+// Kernel-mode tables of one VSS class (one direction sigma) for one target species,
+// [nrho][2][N][N][N/2+1] complex over the stored half k_z <= N/2:
+//   T1(q, k) = w_rho_q w_sigma F(mode of k, rho_q, sigma_eff) / N^3,
+//   T2(q, k) = conj of the same at the mode of the mirror index (-k) mod N,
+// sigma_eff = sigma for the class's own ordering (i, j) and -sigma for the target j of an
+// unlike class (its products are those of (j, i) at -sigma).  A like class that keeps one
+// of each antipodal pair adds F(k, -sigma) = conj F(k, sigma): 2 Re F.  T2 differs from T1
+// only where k has a component at the Nyquist index, whose mirror is not the mode -k.
+void vss_table(const dgfs_plan& P, const dgfs::GainClass& c, bool own, const dgfs::PairParams& pp,
+               std::vector<std::complex<double>>& out) {
+    const int N = P.N, KZH = N / 2 + 1, nrho = P.nrho;
+    const double n3 = double(N) * N * N, L = P.L;
+    const bool like_half = c.i == c.j && P.antipodal;
+    const double wsig = 4.0 * kPi / P.M;
+    const size_t nrep = size_t(N) * N * KZH;
+    const size_t base = out.size();
+    out.resize(base + size_t(nrho) * 2 * nrep);
+    auto mode = [N](int idx) { return double(idx < N / 2 ? idx : idx - N); };
+    const double* s0 = &P.sigma[3 * c.dirs[0]];
+    const double sg[3] = {own ? s0[0] : -s0[0], own ? s0[1] : -s0[1], own ? s0[2] : -s0[2]};
+    const int K2 = P.K2;
+    for (int q = 0; q < nrho; ++q) {
+        // j_l(z) per |k|^2, shared by every mode of this radial point
+        const double rho = pp.rho[q];
+        const double zmax = kPi * pp.a * rho * std::sqrt(double(K2 - 1)) / L;
+        const int lmax = dgfs::pre::vss_terms(zmax);
+        dgfs::pre::VssSeries S(pp.alpha, lmax);
+        std::vector<std::vector<double>> jtab(K2);
+        std::vector<int> nterm(K2);
+        for (int k2 = 0; k2 < K2; ++k2) {
+            const double z = kPi * pp.a * rho * std::sqrt(double(k2)) / L;
+            nterm[k2] = std::min(lmax, dgfs::pre::vss_terms(z)) + 1;
+            dgfs::pre::sph_bessel(nterm[k2] - 1, z, jtab[k2]);
+        }
+        const double pref = pp.C * std::pow(rho, pp.gamma + 2.0) * pp.wrho[q] * wsig / n3;
+        auto Feff = [&](const double k[3]) {
+            const int k2 = int(std::lround(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]));
+            const double mu = k2 > 0 ? (k[0] * sg[0] + k[1] * sg[1] + k[2] * sg[2]) / std::sqrt(double(k2)) : 0.0;
+            double re, im;
+            dgfs::pre::vss_sum(S, jtab[k2].data(), nterm[k2], mu, re, im);
+            return like_half ? std::complex<double>(2.0 * re, 0.0) : std::complex<double>(re, im);
+        };
+        std::complex<double>* t1 = &out[base + (size_t(q) * 2 + 0) * nrep];
+        std::complex<double>* t2 = &out[base + (size_t(q) * 2 + 1) * nrep];
+        for (int kx = 0; kx < N; ++kx)
+            for (int ky = 0; ky < N; ++ky)
+                for (int kz = 0; kz < KZH; ++kz) {
+                    const size_t o = (size_t(kx) * N + ky) * KZH + kz;
+                    const double k[3] = {mode(kx), mode(ky), mode(kz)};
+                    const std::complex<double> v = Feff(k);
+                    t1[o] = pref * v;
+                    if (kx == N / 2 || ky == N / 2 || kz == N / 2) {
+                        const double km[3] = {mode((N - kx) % N), mode((N - ky) % N), mode((N - kz) % N)};
+                        t2[o] = pref * std::conj(Feff(km));
+                    } else {
+                        t2[o] = t1[o];  // F(-k) = conj F(k)
+                    }
+                }
+    }
+}
+
 template <typename T>
 void build_tables(dgfs_plan& P, std::vector<char>& blob) {
     const int N = P.N, s = P.s, nrho = P.nrho, CH = P.geo.CH, NP = N / CH;
@@ -205,24 +265,10 @@ void build_tables(dgfs_plan& P, std::vector<char>& blob) {
         cls.insert(cls.end(), {c.i, c.j, c.ndir, c.dir_offset});
         wdir.push_back(c.weight);
     }
-    // directions per class (rebuilt the same way as in plan creation)
     for (size_t k = 0; k < P.classes.size(); ++k) {
         const auto& c = P.classes[k];
         const dgfs::PairParams& pp = P.pair[c.i * s + c.j];
-        std::vector<int> dirs;
-        if (c.i == c.j && P.antipodal) {
-            for (int p = 0; p < P.M; ++p) {
-                int anti = -1;
-                for (int q = 0; q < P.M; ++q) {
-                    double d = 0;
-                    for (int e = 0; e < 3; ++e) d += std::fabs(P.sigma[3 * p + e] + P.sigma[3 * q + e]);
-                    if (d < 1e-12) anti = q;
-                }
-                if (anti > p) dirs.push_back(p);
-            }
-        } else {
-            for (int p = 0; p < P.M; ++p) dirs.push_back(p);
-        }
+        const std::vector<int>& dirs = c.dirs;
         for (int d = 0; d < c.ndir; ++d) {
             const int gd = c.dir_offset + d;
             const double* sg = &P.sigma[3 * dirs[d]];
@@ -261,6 +307,7 @@ void build_tables(dgfs_plan& P, std::vector<char>& blob) {
     const int K2 = P.K2;
     const double n3 = double(N) * N * N;
     std::vector<double> F;
+    std::vector<std::complex<double>> Fv;
     std::vector<std::vector<int>> ftab(P.classes.size(), std::vector<int>(s, -1));
     int nft = 0;
     for (size_t k = 0; k < P.classes.size(); ++k) {
@@ -271,10 +318,15 @@ void build_tables(dgfs_plan& P, std::vector<char>& blob) {
             const int other = tg == c.i ? c.j : c.i;
             if (!P.mask[tg * s + other]) continue;
             const dgfs::PairParams& pp = P.pair[tg * s + other];
-            for (int q = 0; q < nrho; ++q)
-                for (int k2 = 0; k2 < K2; ++k2)
-                    F.push_back(pp.wrho[q] *
-                                dgfs::pre::kernel_mode(std::sqrt(double(k2)), pp.rho[q], pp.a, pp.gamma, pp.C, L) / n3);
+            if (P.vss) {
+                vss_table(P, c, tg == c.i, pp, Fv);
+            } else {
+                for (int q = 0; q < nrho; ++q)
+                    for (int k2 = 0; k2 < K2; ++k2)
+                        F.push_back(pp.wrho[q] *
+                                    dgfs::pre::kernel_mode(std::sqrt(double(k2)), pp.rho[q], pp.a, pp.gamma, pp.C, L) /
+                                    n3);
+            }
             ftab[k][tg] = nft++;
         }
     }
@@ -288,10 +340,12 @@ void build_tables(dgfs_plan& P, std::vector<char>& blob) {
                 continue;
             }
             for (int k2 = 0; k2 < K2; ++k2)
-                G[size_t(i * s + j) * K2 + k2] = dgfs::pre::loss_weight(std::sqrt(double(k2)), pp.R, pp.gamma, pp.C, L);
+                G[size_t(i * s + j) * K2 + k2] = dgfs::pre::loss_weight(std::sqrt(double(k2)), pp.R, pp.gamma, pp.C, L) *
+                                                 dgfs::pre::vss_loss_factor(pp.alpha);
         }
     P.ngtab = s * s;
-    push_real<T>(blob, P.off_F, F);
+    if (P.vss) push_cplx<T>(blob, P.off_F, Fv);
+    else push_real<T>(blob, P.off_F, F);
     push_real<T>(blob, P.off_G, G);
 
     // ---------------- chunk-combine twiddles e^{-2 pi i kx c / N}, [N][CH]
@@ -301,14 +355,6 @@ void build_tables(dgfs_plan& P, std::vector<char>& blob) {
     push_cplx<T>(blob, P.off_tw, tw);
 
     // ---------------- slots: summed (one per species) and per ordered pair
-    auto cls_of = [&](int i, int j) {
-        for (size_t k = 0; k < P.classes.size(); ++k) {
-            const auto& c = P.classes[k];
-            if (c.i == i && c.j == j) return int(k);
-            if (P.antipodal && c.i == j && c.j == i) return int(k);
-        }
-        return -1;
-    };
     {
         dgfs::SlotSet& S = P.sum_slots;
         S = dgfs::SlotSet();
@@ -336,10 +382,14 @@ void build_tables(dgfs_plan& P, std::vector<char>& blob) {
                     S.slots.insert(S.slots.end(), {i, g0, 0, l0, 0});
                     continue;
                 }
-                const int k = cls_of(i, j);
-                S.gterms.insert(S.gterms.end(), {k, ftab[k][i]});
+                // every class of the pair (one, or with a VSS kernel one per direction)
+                for (size_t k = 0; k < P.classes.size(); ++k) {
+                    const auto& c = P.classes[k];
+                    const bool of_pair = (c.i == i && c.j == j) || (P.antipodal && c.i == j && c.j == i);
+                    if (of_pair && ftab[k][i] >= 0) S.gterms.insert(S.gterms.end(), {int(k), ftab[k][i]});
+                }
                 S.lterms.insert(S.lterms.end(), {j, i * s + j});
-                S.slots.insert(S.slots.end(), {i, g0, 1, l0, 1});
+                S.slots.insert(S.slots.end(), {i, g0, int(S.gterms.size() / 2) - g0, l0, 1});
             }
         push_int(blob, S.off_slots, S.slots);
         push_int(blob, S.off_gterms, S.gterms);
@@ -414,6 +464,7 @@ dgfs_status create_single(const dgfs_problem* problem, const std::vector<unsigne
     P->K2 = 3 * (P->N / 2) * (P->N / 2) + 1;
     for (int i = 0; i < P->s; ++i)
         for (int j = 0; j < P->s; ++j) P->pair.push_back(pair_params(problem, i, j));
+    for (const auto& pp : P->pair) P->vss = P->vss || pp.alpha != 1.0;
     // gain classes of the pairs this plan evaluates (the mask is symmetric)
     int off = 0;
     const double w = 4.0 * kPi / P->M;
@@ -427,11 +478,36 @@ dgfs_status create_single(const dgfs_problem* problem, const std::vector<unsigne
             c.a = P->pair[i * P->s + j].a;
             c.b = P->pair[i * P->s + j].b;
             const bool half = P->antipodal && i == j;
-            c.ndir = half ? P->M / 2 : P->M;
-            c.weight = half ? 2.0 * w : w;
-            c.dir_offset = off;
-            off += c.ndir;
-            P->classes.push_back(c);
+            std::vector<int> dirs;
+            for (int p = 0; p < P->M; ++p) {
+                if (half) {  // keep the first of each antipodal pair
+                    int anti = -1;
+                    for (int q = 0; q < P->M; ++q) {
+                        double d = 0;
+                        for (int e = 0; e < 3; ++e) d += std::fabs(P->sigma[3 * p + e] + P->sigma[3 * q + e]);
+                        if (d < 1e-12) anti = q;
+                    }
+                    if (anti < p) continue;
+                }
+                dirs.push_back(p);
+            }
+            if (!P->vss) {
+                c.dirs = dirs;
+                c.ndir = int(dirs.size());
+                c.weight = half ? 2.0 * w : w;
+                c.dir_offset = off;
+                off += c.ndir;
+                P->classes.push_back(c);
+                continue;
+            }
+            for (int d : dirs) {
+                c.dirs.assign(1, d);
+                c.ndir = 1;
+                c.weight = 1.0;
+                c.dir_offset = off;
+                off += c.ndir;
+                P->classes.push_back(c);
+            }
         }
     P->total_dirs = off;
 
@@ -618,9 +694,11 @@ size_t dgfs_plan::ws_per_node(bool pairs) const {
         return best;
     }
     const size_t c = 2 * elem() * n3();
-    const size_t half = 2 * elem() * size_t(N) * N * (N / 2 + 1);  // a Hermitian-half partial
+    // a partial: the Hermitian half of a real field's spectrum, or (VSS) the whole
+    // spectrum of the complex field S_0 + i S_1
+    const size_t part = vss ? 2 * elem() * n3() : 2 * elem() * size_t(N) * N * (N / 2 + 1);
     const int nslots = pairs ? s * s : s;
-    return c * (size_t(s) + 2 * size_t(nslots)) + half * classes.size() * size_t(nrho);
+    return c * (size_t(s) + 2 * size_t(nslots)) + part * classes.size() * size_t(nrho);
 }
 
 extern "C" {
@@ -656,7 +734,8 @@ dgfs_status dgfs_pair_tables(const dgfs_problem* problem, int32_t i, int32_t j, 
     if (loss) {
         const int K2 = 3 * (problem->N / 2) * (problem->N / 2) + 1;
         for (int k2 = 0; k2 < K2; ++k2)
-            loss[k2] = dgfs::pre::loss_weight(std::sqrt(double(k2)), pp.R, pp.gamma, pp.C, pair_box(problem, i, j));
+            loss[k2] = dgfs::pre::loss_weight(std::sqrt(double(k2)), pp.R, pp.gamma, pp.C, pair_box(problem, i, j)) *
+                       dgfs::pre::vss_loss_factor(pp.alpha);
     }
     return DGFS_OK;
 }
@@ -768,6 +847,7 @@ dgfs_status dgfs_collide_plain(const dgfs_plan* plan, const double* f, double* Q
     if (!plan) return fail(DGFS_EINVAL, "plan is NULL");
     if (plan->precision != DGFS_FP64) return fail(DGFS_EUNSUPPORTED, "the plain path needs an FP64 plan");
     if (!plan->parts.empty()) return fail(DGFS_EUNSUPPORTED, "the plain path has one common grid");
+    if (plan->vss) return fail(DGFS_EUNSUPPORTED, "the plain path covers the VHS family (alpha = 1)");
     if (batch < 0) return fail(DGFS_EINVAL, "batch must be >= 0");
     if (batch == 0) return DGFS_OK;
     if (!f || !Q || !workspace) return fail(DGFS_EINVAL, "f, Q and workspace are required");
@@ -856,6 +936,15 @@ dgfs_status dgfs_relax(const dgfs_plan* plan, void* f, int64_t batch, double dt,
         rc = dev(dgfs::launch_axpby(*plan, f, f1, f, 0.5, 0.5, n, st));
     }
     return rc;
+}
+
+dgfs_status dgfs_kernel_mode(double alpha, double gamma, double C, double a, double L, double rho, const double* k,
+                             const double* sigma, double* F) {
+    if (!k || !sigma || !F) return fail(DGFS_EINVAL, "k, sigma and F are required");
+    if (!(alpha >= 1.0 && alpha <= 2.0)) return fail(DGFS_EINVAL, "alpha must be in [1, 2]");
+    if (!(L > 0.0) || !(rho >= 0.0)) return fail(DGFS_EINVAL, "L must be positive and rho non-negative");
+    dgfs::pre::kernel_mode_vss(k, rho, sigma, a, gamma, alpha, C, L, F[0], F[1]);
+    return DGFS_OK;
 }
 
 dgfs_status dgfs_tile_candidates(int32_t N, int32_t precision, int32_t* pairs, int32_t max_pairs, int32_t* count) {

@@ -29,6 +29,8 @@ struct GainK {
     static constexpr int KZH = N / 2 + 1;               // stored k_z of a partial (Hermitian half)
     static constexpr int NPEN = N * KZH;                // stored (k_y, k_z) pencils of a partial
     static constexpr int PX = (NPEN + NT - 1) / NT;     // stored pencils per thread (guarded)
+    static constexpr int NPENF = N * N;                 // every (k_y, k_z) pencil (VSS: complex field)
+    static constexpr int PXF = (NPENF + NT - 1) / NT;
     static constexpr int ROW = N + 1;                  // padded LDS row (bank spread)
     static constexpr int LDS = NP * N * ROW;
     // packed form: line-data regions [2][NP][N+1], the correction array [N][ROWC] (in
@@ -43,7 +45,8 @@ struct GainK {
 template <typename T>
 struct GainArgs {
     const cx<T>* fhat;  // [nb][s][N^3], DFT / N^3
-    cx<T>* P;           // [nb][ncls][nrho][CH][N/CH][N][N/2+1]  (k_z <= N/2 of each partial)
+    cx<T>* P;           // [nb][ncls][nrho][CH][N/CH][N][N/2+1]  (k_z <= N/2 of each partial);
+                        // VSS: [nb][ncls][nrho][CH][N/CH][N][N]  (the whole spectrum)
     const cx<T>* kx;    // [dirs][nrho][2][CH][N]  x-phase merged with the chunk split
     const cx<T>* yz;    // [dirs][nrho][2][2][N]   y- and z-phases
     const T* nyq;       // [dirs][nrho][2]         2 sin(theta_x N / 2) of the x-phase
@@ -547,9 +550,10 @@ __device__ __forceinline__ void packed_direction(const cx<T>* __restrict__ fa, c
     __syncthreads();
 }
 
-template <typename T, int N, int CH, int CZ, bool PIPE, bool PACK>
+template <typename T, int N, int CH, int CZ, bool PIPE, bool PACK, bool VSS>
 __global__ __launch_bounds__((GainK<T, N, CH, CZ>::NT)) void gain_kernel(GainArgs<T> a) {
     using K = GainK<T, N, CH, CZ>;
+    static_assert(!(PACK && VSS), "the packed two-field form keeps only Re(A B)");
     __shared__ cx<T> buf[K::LDS + ((PACK && pack_ok<T, N, CH, CZ>()) ? K::LINES : 0)];
     // Work items of one node are placed on one XCD (workgroups are dealt to the 8
     // XCDs round-robin), so that node's spectra stay in that XCD's L2.
@@ -573,32 +577,46 @@ __global__ __launch_bounds__((GainK<T, N, CH, CZ>::NT)) void gain_kernel(GainArg
     const int cz = tid / K::NTC, u = tid % K::NTC;
     const int m = u / N, r = u % N;
 
-    // Only Re(S_q) reaches the result: the radial operator multiplies DFT(S_q) by a
-    // real F that is even in k, so Re IDFT(F DFT(S)) = IDFT(F DFT(Re S)).
-    T S[K::NS];
+    // VHS: only Re(S_q) reaches the result, since the radial operator multiplies
+    // DFT(S_q) by a real F that is even in k: Re IDFT(F DFT(S)) = IDFT(F DFT(Re S)).
+    // VSS: F depends on the direction and, at indices with a Nyquist component, F at the
+    // mode of k is not the conjugate of F at the mode of the mirror index, so the
+    // imaginary part of S (from the Nyquist modes of the shifted fields) contributes:
+    // the class's one direction keeps S = S + i S1 whole.
+    T S[K::NS], S1[VSS ? K::NS : 1];
 #pragma unroll
     for (int n = 0; n < K::NS; ++n) S[n] = T(0);
+#pragma unroll
+    for (int n = 0; n < (VSS ? K::NS : 1); ++n) S1[n] = T(0);
 
-    for (int d = 0; d < ndir; ++d) {
+    auto direction = [&](int d, T* Sd) {
         const int64_t base = (int64_t(doff + d) * a.nrho + q) * 2;
         if constexpr (PACK && pack_ok<T, N, CH, CZ>()) {
             packed_direction<T, N, CH, CZ, PIPE>(fhi, fhj, a.kx + ((base + 0) * CH + c) * N, a.yz + (base + 0) * 2 * N,
                                                  a.nyq[base], a.kx + ((base + 1) * CH + c) * N,
-                                                 a.yz + (base + 1) * 2 * N, a.nyq[base + 1], c, buf, cz, m, r, w, S);
-            continue;
+                                                 a.yz + (base + 1) * 2 * N, a.nyq[base + 1], c, buf, cz, m, r, w, Sd);
+        } else {
+            cx<T> A[K::NS], B[K::NS];
+            field_ifft<T, N, CH, CZ, PIPE>(fhi, a.kx + ((base + 0) * CH + c) * N, a.yz + (base + 0) * 2 * N,
+                                           a.nyq[base], c, buf, cz, m, r, A);
+            field_ifft<T, N, CH, CZ, PIPE>(fhj, a.kx + ((base + 1) * CH + c) * N, a.yz + (base + 1) * 2 * N,
+                                           a.nyq[base + 1], c, buf, cz, m, r, B);
+#pragma unroll
+            for (int n = 0; n < K::NS; ++n) Sd[n] = fma(w, fma(A[n].x, B[n].x, -A[n].y * B[n].y), Sd[n]);
+            if constexpr (VSS) {
+#pragma unroll
+                for (int n = 0; n < K::NS; ++n) S1[n] = fma(w, fma(A[n].x, B[n].y, A[n].y * B[n].x), S1[n]);
+            }
         }
-        cx<T> A[K::NS], B[K::NS];
-        field_ifft<T, N, CH, CZ, PIPE>(fhi, a.kx + ((base + 0) * CH + c) * N, a.yz + (base + 0) * 2 * N, a.nyq[base],
-                                 c, buf, cz, m, r, A);
-        field_ifft<T, N, CH, CZ, PIPE>(fhj, a.kx + ((base + 1) * CH + c) * N, a.yz + (base + 1) * 2 * N,
-                                 a.nyq[base + 1], c, buf, cz, m, r, B);
-#pragma unroll
-        for (int n = 0; n < K::NS; ++n) S[n] = fma(w, fma(A[n].x, B[n].x, -A[n].y * B[n].y), S[n]);
-    }
+    };
+    for (int d = 0; d < ndir; ++d) direction(d, S);
 
-    // forward DFT of Re S_q: z and y through LDS, then the chunk's part of x
+    // forward DFT of Re S_q (VSS: of S + i S1): z and y through LDS, then the chunk's part of x
 #pragma unroll
-    for (int j = 0; j < K::NS; ++j) buf[(m * N + r) * K::ROW + CZ * j + cz] = cx<T>{S[j], T(0)};
+    for (int j = 0; j < K::NS; ++j) {
+        if constexpr (VSS) buf[(m * N + r) * K::ROW + CZ * j + cz] = cx<T>{S[j], S1[j]};
+        else buf[(m * N + r) * K::ROW + CZ * j + cz] = cx<T>{S[j], T(0)};
+    }
     __syncthreads();
     {
         cx<T> v[K::NS];
@@ -616,6 +634,24 @@ __global__ __launch_bounds__((GainK<T, N, CH, CZ>::NT)) void gain_kernel(GainArg
 #pragma unroll
         for (int j = 0; j < K::NS; ++j) buf[(m * N + CZ * j + cz) * K::ROW + r] = v[j];
         __syncthreads();
+    }
+    if constexpr (VSS) {
+        // the transform of a complex field: every (k_y, k_z) pencil is stored
+        constexpr int64_t PCHF = int64_t(K::NP) * K::NPENF;
+        cx<T>* Pout = a.P + ((int64_t(b) * a.ncls + cl) * a.nrho + q) * (CH * PCHF) + int64_t(c) * PCHF;
+#pragma unroll 1
+        for (int k = 0; k < K::PXF; ++k) {
+            const int P = tid + k * K::NT;
+            if (K::PXF * K::NT != K::NPENF && P >= K::NPENF) break;
+            const int ky = P / N, kz = P % N;
+            cx<T> v[K::NP];
+#pragma unroll
+            for (int mm = 0; mm < K::NP; ++mm) v[mm] = buf[(mm * N + ky) * K::ROW + kz];
+            fft<K::NP, -1>(v);
+#pragma unroll
+            for (int kk = 0; kk < K::NP; ++kk) Pout[kk * K::NPENF + P] = v[kk];
+        }
+        return;
     }
     // The chunk's partial is the DFT of a real array over (x-planes of the chunk, y, z),
     // so it is Hermitian in (k_xp, k_y, k_z): only k_z <= N/2 is stored, the radial kernel
@@ -644,6 +680,8 @@ struct RadialArgs {
     cx<T>* Gt;          // [nb][nslots][N^3]
     cx<T>* Lt;          // [nb][nslots][N^3]
     const T* F;         // [nftab][nrho][K2]  w_q F(|k|, rho_q) / N^3
+    const cx<T>* Fv;    // VSS: [nftab][nrho][2][N][N][N/2+1]  T1, T2 (w_q w_sigma F / N^3 at k, and the
+                        //      conjugate at the mirror index)
     const T* G;         // [ngtab][K2]        G-(|k|)
     const cx<T>* tw;    // [N][CH]  e^{-2 pi i kx c / N}
     const int* slots;   // [nslots][5]
@@ -658,7 +696,11 @@ struct RadialArgs {
 // L(k) = sum_j G-(|k|) f_hat^j(k) for the CH x-modes k_x = k_xp + j N/CH, and writes
 // both at k and their conjugates at -k (S_q and f are real, F and G- are real and even
 // in k).  Pairs with k_z = 0 or N/2 lie wholly in the stored half and are written once.
-template <typename T, int N, int CH>
+// VSS: each class (one direction) partial is the whole spectrum Z of the complex S; the
+// Hermitian part of F(mode of k) Z(k), the part that reaches the real result, is
+// (T1(k) Z(k) + T2(k) conj Z(-k)) / 2 with T1 = F at the mode of k and T2 = conj F at the
+// mode of the mirror index (-k) mod N; the thread reads Z at k and -k.
+template <typename T, int N, int CH, bool VSS>
 __global__ __launch_bounds__(256) void radial_kernel(RadialArgs<T> a) {
     constexpr int NP = N / CH;
     constexpr int KZH = N / 2 + 1;
@@ -686,7 +728,42 @@ __global__ __launch_bounds__(256) void radial_kernel(RadialArgs<T> a) {
     cx<double> acc[CH];
 #pragma unroll
     for (int j = 0; j < CH; ++j) acc[j] = cx<double>{0.0, 0.0};
-    for (int gi = 0; gi < ng; ++gi) {
+    if constexpr (VSS) {
+        constexpr int64_t PCHF = int64_t(NP) * N2, NREP = N2 * KZH;
+        const int kxpm = (NP - kxp) % NP, kym = (N - ky) % N, kzm = (N - kz) % N;
+        const int64_t eP = (int64_t(kxp) * N + ky) * N + kz, ePm = (int64_t(kxpm) * N + kym) * N + kzm;
+        for (int gi = 0; gi < ng; ++gi) {
+            const int cl = a.gterms[2 * (g0 + gi)], ft = a.gterms[2 * (g0 + gi) + 1];
+            const cx<T>* Pb = a.P + (int64_t(b) * a.ncls + cl) * a.nrho * (CH * PCHF);
+            const cx<T>* Fb = a.Fv + int64_t(ft) * a.nrho * 2 * NREP + (int64_t(kxp) * N + ky) * KZH + kz;
+            for (int q = 0; q < a.nrho; ++q) {
+                cx<T> pc[CH], pm[CH];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    pc[c] = Pb[int64_t(q) * (CH * PCHF) + c * PCHF + eP];
+                    pm[c] = Pb[int64_t(q) * (CH * PCHF) + c * PCHF + ePm];
+                }
+#pragma unroll
+                for (int j = 0; j < CH; ++j) {
+                    const int kx = kxp + j * NP, kxm = (N - kx) % N;
+                    cx<T> Z = pc[0], Zm = pm[0];
+#pragma unroll
+                    for (int c = 1; c < CH; ++c) {
+                        cmac(Z, a.tw[kx * CH + c], pc[c]);
+                        cmac(Zm, a.tw[kxm * CH + c], pm[c]);
+                    }
+                    const cx<T> t1 = Fb[(int64_t(q) * 2 + 0) * NREP + int64_t(j) * NP * N * KZH];
+                    const cx<T> t2 = Fb[(int64_t(q) * 2 + 1) * NREP + int64_t(j) * NP * N * KZH];
+                    // t1 Z + t2 conj(Zm), halved
+                    acc[j].x += 0.5 * (double(t1.x) * Z.x - double(t1.y) * Z.y + double(t2.x) * Zm.x +
+                                       double(t2.y) * Zm.y);
+                    acc[j].y += 0.5 * (double(t1.x) * Z.y + double(t1.y) * Z.x - double(t2.x) * Zm.y +
+                                       double(t2.y) * Zm.x);
+                }
+            }
+        }
+    }
+    for (int gi = 0; gi < (VSS ? 0 : ng); ++gi) {
         const int cl = a.gterms[2 * (g0 + gi)], ft = a.gterms[2 * (g0 + gi) + 1];
         const cx<T>* Pb = a.P + (int64_t(b) * a.ncls + cl) * a.nrho * (CH * PCH) + e;
         const T* Ft = a.F + int64_t(ft) * a.nrho * a.K2;
@@ -760,7 +837,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // ev (optional): 6 events recorded at the stage boundaries (start, after forward FFT,
 // after gain, after radial, after inverse FFTs, after combine).
-template <typename T, int N, int CH, int CZ, bool PIPE, bool PACK>
+template <typename T, int N, int CH, int CZ, bool PIPE, bool PACK, bool VSS>
 hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, bool pairs, hipStream_t st,
                      hipEvent_t* ev) {
     auto mark = [&](int k) {
@@ -773,7 +850,7 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
     cx<T>* fhat = reinterpret_cast<cx<T>*>(w);
     w += align256(sizeof(cx<T>) * nb * p.s * N3);
     cx<T>* P = reinterpret_cast<cx<T>*>(w);
-    w += align256(sizeof(cx<T>) * int64_t(nb) * ncls * p.nrho * (N3 / N) * (N / 2 + 1));
+    w += align256(sizeof(cx<T>) * int64_t(nb) * ncls * p.nrho * (VSS ? N3 : (N3 / N) * (N / 2 + 1)));
     cx<T>* Gt = reinterpret_cast<cx<T>*>(w);
     cx<T>* Lt = Gt + int64_t(nb) * ss.nslots * N3;  // contiguous with Gt
 
@@ -797,7 +874,7 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
     ga.nb = nb;
     const int64_t ipn = int64_t(ncls) * p.nrho * CH;
     const int64_t groups = ((nb + 7) / 8) * 8 * ipn;
-    gain_kernel<T, N, CH, CZ, PIPE, PACK><<<dim3(unsigned(groups)), dim3(GainK<T, N, CH, CZ>::NT), 0, st>>>(ga);
+    gain_kernel<T, N, CH, CZ, PIPE, PACK, VSS><<<dim3(unsigned(groups)), dim3(GainK<T, N, CH, CZ>::NT), 0, st>>>(ga);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     mark(2);
 
@@ -807,6 +884,7 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
     ra.Gt = Gt;
     ra.Lt = Lt;
     ra.F = reinterpret_cast<const T*>(dev + p.off_F);
+    ra.Fv = reinterpret_cast<const cx<T>*>(dev + p.off_F);
     ra.G = reinterpret_cast<const T*>(dev + p.off_G);
     ra.tw = reinterpret_cast<const cx<T>*>(dev + p.off_tw);
     ra.slots = reinterpret_cast<const int*>(dev + ss.off_slots);
@@ -819,7 +897,7 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
     ra.nslots = ss.nslots;
     ra.K2 = p.K2;
     const int64_t rthreads = int64_t(nb) * ss.nslots * (N / CH) * N * (N / 2 + 1);
-    radial_kernel<T, N, CH><<<dim3(unsigned((rthreads + 255) / 256)), dim3(256), 0, st>>>(ra);
+    radial_kernel<T, N, CH, VSS><<<dim3(unsigned((rthreads + 255) / 256)), dim3(256), 0, st>>>(ra);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     mark(3);
 
@@ -846,5 +924,14 @@ hipError_t run_tiles_32(const dgfs_plan& p, const void* f, void* Q, int nb, void
                         hipEvent_t* ev);
 hipError_t run_tiles_48(const dgfs_plan& p, const void* f, void* Q, int nb, void* ws, bool pairs, hipStream_t st,
                         hipEvent_t* ev);
+// The same for plans with a VSS kernel (vss_<N>.hip).
+hipError_t run_vss_16(const dgfs_plan& p, const void* f, void* Q, int nb, void* ws, bool pairs, hipStream_t st,
+                      hipEvent_t* ev);
+hipError_t run_vss_24(const dgfs_plan& p, const void* f, void* Q, int nb, void* ws, bool pairs, hipStream_t st,
+                      hipEvent_t* ev);
+hipError_t run_vss_32(const dgfs_plan& p, const void* f, void* Q, int nb, void* ws, bool pairs, hipStream_t st,
+                      hipEvent_t* ev);
+hipError_t run_vss_48(const dgfs_plan& p, const void* f, void* Q, int nb, void* ws, bool pairs, hipStream_t st,
+                      hipEvent_t* ev);
 
 }  // namespace dgfs

@@ -144,6 +144,15 @@ bool gain_geometry(int N, int precision, GainGeometry* g) { return tile_candidat
 
 hipError_t launch_collide(const dgfs_plan& p, const void* f, void* Q, int64_t nb, void* ws, bool pairs,
                           hipStream_t st, hipEvent_t* ev) {
+    if (p.vss) {
+        switch (p.N) {
+            case 16: return run_vss_16(p, f, Q, int(nb), ws, pairs, st, ev);
+            case 24: return run_vss_24(p, f, Q, int(nb), ws, pairs, st, ev);
+            case 32: return run_vss_32(p, f, Q, int(nb), ws, pairs, st, ev);
+            case 48: return run_vss_48(p, f, Q, int(nb), ws, pairs, st, ev);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (p.N) {
         case 16: return run_tiles_16(p, f, Q, int(nb), ws, pairs, st, ev);
         case 24: return run_tiles_24(p, f, Q, int(nb), ws, pairs, st, ev);

@@ -27,16 +27,21 @@ int tile_candidates(int N, int precision, GainGeometry* out, int max);  // compi
 // One "gain class": the S_q field sum_p w A_p B_p with A = f^i shifted by +a rho sigma_p,
 // B = f^j shifted by -b rho sigma_p.  With an antipodal design one class serves both
 // orderings of an unlike pair, and a like pair needs only half of the directions.
+//
+// With a VSS kernel the kernel mode depends on sigma, so the directions are not summed:
+// a class holds one direction, whose complex product S is transformed whole, and the
+// sphere weight goes into the kernel-mode tables.
 struct GainClass {
     int i, j;
     double a, b;
     int ndir;        // directions of this class
     int dir_offset;  // first global direction index in the phase tables
-    double weight;   // sphere weight per direction (4 pi / M, doubled for a halved like pair)
+    double weight;   // sphere weight per direction (4 pi / M, doubled for a halved like pair; 1 for VSS)
+    std::vector<int> dirs;  // design point of each direction
 };
 
 struct PairParams {
-    double a, b, gamma, C, R;
+    double a, b, gamma, C, R, alpha;
     std::vector<double> rho, wrho;
 };
 
@@ -62,6 +67,7 @@ struct dgfs_plan {
     dgfs::GainGeometry geo{};
     std::vector<double> sigma;  // design, [M][3]
     bool antipodal = false;
+    bool vss = false;           // some pair has alpha > 1: sigma-dependent kernel-mode tables
     std::vector<dgfs::PairParams> pair;  // [s*s]
     std::vector<dgfs::GainClass> classes;
     int total_dirs = 0;

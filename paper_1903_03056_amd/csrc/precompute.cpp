@@ -150,6 +150,90 @@ double kernel_mode(double kabs, double rho, double a, double gamma, double C, do
     return 4.0 * kPi * C * std::pow(rho, gamma + 2.0) * sinc(kPi * a * rho * kabs / L);
 }
 
+VssSeries::VssSeries(double alpha_, int lmax) : alpha(alpha_), lam(size_t(lmax) + 1) {
+    const double beta = alpha - 1.0;
+    double l0 = 2.0 * kPi * std::pow(2.0, alpha) / alpha;
+    for (int l = 0; l <= lmax; ++l) {
+        lam[l] = (2.0 * l + 1.0) * l0;
+        l0 *= (beta - l) / (beta + l + 2.0);
+    }
+}
+
+int vss_terms(double z) {
+    // j_l(z) < 1e-17 |j|_max well before l = z + 9 z^{1/3} + 30
+    return int(z + 9.0 * std::cbrt(z) + 30.0);
+}
+
+void sph_bessel(int lmax, double z, std::vector<double>& j) {
+    j.assign(size_t(lmax) + 1, 0.0);
+    if (z == 0.0) {
+        j[0] = 1.0;
+        return;
+    }
+    // Miller: recur j_{l-1} = (2l+1)/z j_l - j_{l+1} downwards from far above
+    // max(lmax, z), where the minimal solution dominates, then normalise by j_0 or j_1
+    // (they never vanish together).
+    const int top = std::max(lmax, int(z)) + int(std::sqrt(160.0 * (std::max(lmax, int(z)) + 1))) + 20;
+    double jp = 0.0, jc = 1e-300;
+    for (int l = top; l >= 1; --l) {
+        const double jm = (2.0 * l + 1.0) / z * jc - jp;
+        jp = jc;
+        jc = jm;
+        if (l - 1 <= lmax) j[l - 1] = jc;
+        if (std::fabs(jc) > 1e250) {  // rescale what is stored and the recurrence state
+            jc *= 1e-250;
+            jp *= 1e-250;
+            for (int m = l - 1; m <= lmax; ++m) j[m] *= 1e-250;
+        }
+    }
+    const double s = std::sin(z), c = std::cos(z);
+    const double j0 = s / z, j1 = s / (z * z) - c / z;
+    double scale;
+    if (std::fabs(j0) >= std::fabs(j1) || lmax < 1) scale = j0 / j[0];
+    else scale = j1 / j[1];
+    for (double& v : j) v *= scale;
+}
+
+void vss_sum(const VssSeries& S, const double* j, int nterms, double mu, double& re, double& im) {
+    // (-i)^l cycles 1, -i, -1, i; P_l(mu) by the three-term recurrence
+    double p0 = 1.0, p1 = mu;
+    double r = 0.0, i = 0.0;
+    for (int l = 0; l < nterms; ++l) {
+        const double pl = l == 0 ? p0 : p1;
+        const double t = S.lam[l] * j[l] * pl;
+        switch (l & 3) {
+            case 0: r += t; break;
+            case 1: i -= t; break;
+            case 2: r -= t; break;
+            default: i += t; break;
+        }
+        if (l >= 1) {
+            const double pn = ((2.0 * l + 1.0) * mu * p1 - l * p0) / (l + 1.0);
+            p0 = p1;
+            p1 = pn;
+        }
+    }
+    re = r;
+    im = i;
+}
+
+void kernel_mode_vss(const double k[3], double rho, const double sigma[3], double a, double gamma, double alpha,
+                     double C, double L, double& re, double& im) {
+    const double kabs = std::sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+    const double mu = kabs > 0.0 ? (k[0] * sigma[0] + k[1] * sigma[1] + k[2] * sigma[2]) / kabs : 0.0;
+    const double z = kPi * a * rho * kabs / L;
+    const int n = vss_terms(z);
+    VssSeries S(alpha, n);
+    std::vector<double> j;
+    sph_bessel(n, z, j);
+    vss_sum(S, j.data(), n + 1, mu, re, im);
+    const double f = C * std::pow(rho, gamma + 2.0);
+    re *= f;
+    im *= f;
+}
+
+double vss_loss_factor(double alpha) { return std::pow(2.0, alpha - 1.0) / alpha; }
+
 namespace {
 // 20-point Gauss-Legendre on [-1, 1], built once.
 struct GL20 {

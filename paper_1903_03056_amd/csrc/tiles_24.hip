@@ -10,17 +10,17 @@ hipError_t run_tiles_24(const dgfs_plan& p, const void* f, void* Q, int nb, void
     const int key = p.geo.CH * 100 + p.geo.CZ;
     if (p.precision == DGFS_FP64) {
         switch (key) {
-            case 302: return detail::run_slice<double, 24, 3, 2, false, false>(
+            case 302: return detail::run_slice<double, 24, 3, 2, false, false, false>(
                 p, static_cast<const double*>(f), static_cast<double*>(Q), nb, ws, pairs, st, ev);
             default: return hipErrorInvalidValue;
         }
     }
     switch (key) {
-        case 301: return detail::run_slice<float, 24, 3, 1, false, false>(
+        case 301: return detail::run_slice<float, 24, 3, 1, false, false, false>(
             p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
-        case 302: return detail::run_slice<float, 24, 3, 2, false, false>(
+        case 302: return detail::run_slice<float, 24, 3, 2, false, false, false>(
             p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
-        case 304: return detail::run_slice<float, 24, 3, 4, false, false>(
+        case 304: return detail::run_slice<float, 24, 3, 4, false, false, false>(
             p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
         default: return hipErrorInvalidValue;
     }

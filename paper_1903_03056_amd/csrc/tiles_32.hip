@@ -10,17 +10,17 @@ hipError_t run_tiles_32(const dgfs_plan& p, const void* f, void* Q, int nb, void
     const int key = p.geo.CH * 100 + p.geo.CZ;
     if (p.precision == DGFS_FP64) {
         switch (key) {
-            case 402: return detail::run_slice<double, 32, 4, 2, false, false>(
+            case 402: return detail::run_slice<double, 32, 4, 2, false, false, false>(
                 p, static_cast<const double*>(f), static_cast<double*>(Q), nb, ws, pairs, st, ev);
             default: return hipErrorInvalidValue;
         }
     }
     switch (key) {
-        case 201: return detail::run_slice<float, 32, 2, 1, true, false>(
+        case 201: return detail::run_slice<float, 32, 2, 1, true, false, false>(
             p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
-        case 401: return detail::run_slice<float, 32, 4, 1, false, false>(
+        case 401: return detail::run_slice<float, 32, 4, 1, false, false, false>(
             p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
-        case 402: return detail::run_slice<float, 32, 4, 2, true, false>(
+        case 402: return detail::run_slice<float, 32, 4, 2, true, false, false>(
             p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
         default: return hipErrorInvalidValue;
     }

@@ -58,7 +58,9 @@ def test_check_problem_accepts_and_rejects():
     bad[0][0] = (0.3, 1.0, 1.0)                                          # omega out of range
     assert check_problem(m, 6.0, 32, 12, 16, bad) == DGFS_EINVAL
     vss = [[(0.74, 1.4, 1.0)] * 2 for _ in range(2)]
-    assert check_problem(m, 6.0, 32, 12, 16, vss) == DGFS_EUNSUPPORTED   # VSS not implemented
+    assert check_problem(m, 6.0, 32, 12, 16, vss) == DGFS_OK             # VSS
+    vss[0][0] = (0.74, 2.5, 1.0)
+    assert check_problem(m, 6.0, 32, 12, 16, vss) == DGFS_EINVAL         # alpha out of range
     assert check_problem(m, 6.0, 20, 12, 16, k) == DGFS_EUNSUPPORTED     # no kernels for N=20
     assert check_problem(m, 6.0, 32, 12, 16, k, "f64") == DGFS_OK
     assert check_problem(m, 6.0, 48, 24, 24, k) == DGFS_OK
@@ -153,3 +155,34 @@ def test_pair_tables_use_the_pair_box_with_species_grids():
             k2 = np.arange(3 * 8 ** 2 + 1)
             ref = OS.loss_weight(np.sqrt(k2), t["R"], t["gamma"], t["C"], Lij)
             assert np.abs(t["loss_by_k2"] - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("alpha", [1.0, 1.32, 1.36, 1.4, 2.0])
+def test_vss_kernel_mode_matches_oracle(alpha):
+    """The library's kernel mode (Funk-Hecke series with Miller-recurrence Bessel
+    functions) against the oracle's (pole-at-sigma Gauss-Jacobi integral), over modes of
+    an N = 48 grid and radii up to R: within 1e-12 of F(0)."""
+    from oracle import vss as OV
+    from paper_1903_03056_amd import kernel_mode
+    rng = np.random.default_rng(int(alpha * 100))
+    sig = OQ.design_quadrature(24)[0]
+    for trial in range(40):
+        k = rng.integers(-24, 24, size=3).astype(float)
+        sg = sig[trial % 24] if trial % 2 else rng.normal(size=3)
+        sg = sg / np.linalg.norm(sg)
+        rho, a, gamma, C, L = rng.uniform(0, 5.5), rng.uniform(0.02, 0.98), rng.uniform(0, 1), 0.7, 6.0
+        got = kernel_mode(alpha, gamma, C, a, L, rho, k, sg)
+        ref = OV.kernel_mode(k[None, :], rho, sg, a, gamma, alpha, C, L)[0]
+        F0 = C * rho ** (gamma + 2) * 2 * np.pi * 2 ** alpha / alpha
+        assert abs(got - ref) <= 1e-12 * F0, (k, rho, a)
+
+
+def test_vss_loss_table_matches_oracle():
+    """G- of a VSS pair (alpha = 1.36) from the library's tables against the oracle's."""
+    from paper_1903_03056_amd import pair_tables
+    m = (1.0, 2.1)
+    kern = [[(0.805, 1.36, OP.vss_prefactor(m[i], m[j], 0.805, 1.36)) for j in range(2)] for i in range(2)]
+    t = pair_tables(m, 6.0, 32, 12, 16, kern, 0, 1, "f64")
+    R = OP.truncation_radius(6.0, m[0], m[1])
+    ref = OS.loss_weight(np.sqrt(np.arange(3 * 16 ** 2 + 1)), R, 2 * (1 - 0.805), kern[0][1][2], 6.0, alpha=1.36)
+    assert np.abs(t["loss_by_k2"] - ref).max() <= 1e-13 * np.abs(ref).max()
