@@ -13,6 +13,9 @@ Also measured, outside the timed steps (the "workloads" object):
     and replayed (per-replay p50/p99);
   * heavy/light species-specific grids: 1024 nodes, masses (1, 32.75) on boxes
     L_i = 6 sqrt(1/m_i), hard spheres, N=48, M=24 (7-design), N_rho=24;
+  * VSS kernels: the slab shape with the argon-krypton VSS parameters (sigma-dependent
+    kernel mode, one transform per direction);
+  * SSP-RK2 time stepping of the slab (two projected operator evaluations per step);
   * measured ceilings: a device copy (HBM) and an FMA loop (FP32 vector).
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -56,6 +59,16 @@ def gain_flops_per_node(N, M, n_rho, s, antipodal=True):
         dirs = s * s * M
         ncls = s * s
     return dirs * n_rho * (2 * (fft + 6 * n3) + 10 * n3) + ncls * n_rho * fft
+
+
+def gain_flops_per_node_vss(N, M, n_rho, s, antipodal=True):
+    """The same for a VSS kernel, whose kernel mode depends on the direction: per class
+    (one direction), radial point: two inverse 3-D FFTs with their phase products, the
+    complex product-accumulate (12 flops per point) and one forward 3-D FFT."""
+    n3 = N ** 3
+    fft = 5.0 * n3 * math.log2(n3)
+    dirs = s * (M // 2) + (s * (s - 1) // 2) * M if antipodal else s * s * M
+    return dirs * n_rho * (2 * (fft + 6 * n3) + 12 * n3 + fft)
 
 
 def load_traffic():
@@ -206,6 +219,53 @@ def species_grid_leg(torch, dev, calls):
     return res, checks
 
 
+VSS_WORKLOAD = dict(batch=256, masses=(1.0, 139.1 / 66.3), omega=((0.81, 0.805), (0.805, 0.8)),
+                    alpha=((1.4, 1.36), (1.36, 1.32)), N=32, L=6.0, M=12, n_rho=16, noise=1e-2, seed=2)
+
+
+def vss_leg(torch, dev, calls):
+    """The slab shape with the argon-krypton VSS kernels (sigma-dependent kernel mode),
+    FP32; stage times from the timed collide."""
+    from paper_1903_03056_amd import CollisionPlan, vss_kernel
+    from synth import inputs as I
+    w = VSS_WORKLOAD
+    s = len(w["masses"])
+    kern = vss_kernel(w["masses"], w["omega"], w["alpha"])
+    f = I.draw_bimaxwellian_batch(np.random.default_rng(w["seed"]), w["batch"], s, w["N"], w["L"], w["masses"],
+                                  noise=w["noise"]).astype(np.float32)
+    t0 = time.perf_counter()
+    plan = CollisionPlan(w["masses"], w["N"], w["L"], w["M"], w["n_rho"], kernel=kern, precision="f32")
+    setup_s = time.perf_counter() - t0
+    ft = torch.tensor(f, device=dev)
+    ws = plan.workspace(w["batch"], dev)
+    Q = torch.empty_like(ft)
+    plan.collide(ft, out=Q, workspace=ws)
+    torch.cuda.synchronize()
+    stage = np.zeros(5)
+    st = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(calls):
+        _, ms = plan.collide_timed(ft, out=Q, workspace=ws)
+        stage += np.array(ms)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms_call = e0.elapsed_time(e1) / calls
+    stage /= calls
+    flops = w["batch"] * gain_flops_per_node_vss(w["N"], w["M"], w["n_rho"], s)
+    res = {"workload": "VSS slab: 256 nodes, argon-krypton VSS kernels (omega 0.81/0.805/0.8, alpha "
+                       "1.4/1.36/1.32, m2/m1 = 2.098), N=32, L=6, M=12, N_rho=16, bi-Maxwellian + 1e-2 noise, "
+                       "seed 2, FP32",
+           "value": round(w["batch"] * s * s / (ms_call * 1e-3), 1), "unit": "evals/s", "calls": calls,
+           "ms_per_call": round(ms_call, 3),
+           "stages_ms": {"forward_fft": round(stage[0], 4), "gain": round(stage[1], 4),
+                         "radial_loss": round(stage[2], 4), "inverse_fft": round(stage[3], 4),
+                         "combine": round(stage[4], 4)},
+           "gain_tflops": round(flops / (stage[1] * 1e-3) / 1e12, 2),
+           "setup_s": round(setup_s, 2)}
+    return res
+
+
 def relax_leg(torch, dev, plan, f32, w, steps, dt=0.01):
     """SSP-RK2 time stepping of the slab workload (two projected operator evaluations
     per step, all on the device), timed with events around each call."""
@@ -241,6 +301,8 @@ def main():
                     help="leave out the plain per-point FP64 comparison leg (not part of the timed step)")
     ap.add_argument("--no-extra", action="store_true",
                     help="leave out the uneven-batch, species-grid, SSP-RK2 and measured-ceiling legs")
+    ap.add_argument("--only-leg", choices=["vss_slab"], default=None,
+                    help="run only the named extra workload and print its JSON (for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain device copy of 2 x 256 MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -254,6 +316,11 @@ def main():
 
     from paper_1903_03056_amd import CollisionPlan
     from synth import inputs as I
+
+    if args.only_leg == "vss_slab":
+        log("VSS kernels only")
+        print(json.dumps({"vss_slab": vss_leg(torch, torch.device("cuda:0"), args.steps)}), flush=True)
+        return
 
     w = WORKLOAD
     s = len(w["masses"])
@@ -376,6 +443,8 @@ def main():
         log("species-specific grids")
         extra["heavy_light_species_grids"], c = species_grid_leg(torch, dev, 3)
         checks += c
+        log("VSS kernels")
+        extra["vss_slab"] = vss_leg(torch, dev, 5)
         log("SSP-RK2 stepping")
         extra["ssprk2_relax"], c = relax_leg(torch, dev, plan, f32, w, 10)
         checks += c

@@ -15,5 +15,6 @@ from .collision import (  # noqa: F401
     kernel_mode,
     pair_tables,
     vhs_kernel,
+    vss_kernel,
     vhs_prefactor,
 )

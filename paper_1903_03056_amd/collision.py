@@ -54,6 +54,16 @@ def vhs_kernel(masses, omega, alpha: float = 1.0, kn0: float = 1.0):
             for i in range(s)]
 
 
+def vss_kernel(masses, omega, alpha, kn0: float = 1.0):
+    """Kernel of eq. NVSS per ordered pair: omega and alpha are scalars or symmetric
+    [s][s] tables (e.g. a mixture's like and unlike parameters)."""
+    s = len(masses)
+    om = np.broadcast_to(np.asarray(omega, dtype=np.float64), (s, s))
+    al = np.broadcast_to(np.asarray(alpha, dtype=np.float64), (s, s))
+    return [[(float(om[i, j]), float(al[i, j]), vhs_prefactor(masses[i], masses[j], om[i, j], al[i, j], kn0))
+             for j in range(s)] for i in range(s)]
+
+
 def check_problem(masses, L, N, M, n_rho, kernel, precision="f32", L_species=None, tile=None) -> int:
     """Host-side validation; returns the dgfs status code (0 = ok)."""
     h = _ProblemHolder(masses, L, N, M, n_rho, kernel, precision, L_species, tile=tile)

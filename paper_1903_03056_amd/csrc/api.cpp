@@ -250,6 +250,30 @@ void vss_table(const dgfs_plan& P, const dgfs::GainClass& c, bool own, const dgf
     }
 }
 
+// Push a slot set's descriptors, with the per-class view of its gain terms (each class
+// feeds at most two slots: its own ordering and, for an unlike pair, the mirrored one).
+void push_uses(dgfs::SlotSet& S, int ncls, std::vector<char>& blob) {
+    S.cuses.assign(size_t(ncls) * 4, -1);
+    for (int sl = 0; sl < S.nslots; ++sl) {
+        const int g0 = S.slots[5 * sl + 1], ng = S.slots[5 * sl + 2];
+        for (int gi = g0; gi < g0 + ng; ++gi) {
+            const int cl = S.gterms[2 * gi], ft = S.gterms[2 * gi + 1];
+            int* u = &S.cuses[4 * size_t(cl)];
+            if (u[0] < 0) {
+                u[0] = sl;
+                u[1] = ft;
+            } else {
+                u[2] = sl;
+                u[3] = ft;
+            }
+        }
+    }
+    push_int(blob, S.off_slots, S.slots);
+    push_int(blob, S.off_gterms, S.gterms);
+    push_int(blob, S.off_lterms, S.lterms);
+    push_int(blob, S.off_cuses, S.cuses);
+}
+
 template <typename T>
 void build_tables(dgfs_plan& P, std::vector<char>& blob) {
     const int N = P.N, s = P.s, nrho = P.nrho, CH = P.geo.CH, NP = N / CH;
@@ -367,9 +391,7 @@ void build_tables(dgfs_plan& P, std::vector<char>& blob) {
                 if (P.mask[i * s + j]) S.lterms.insert(S.lterms.end(), {j, i * s + j});
             S.slots.insert(S.slots.end(), {i, g0, int(S.gterms.size() / 2) - g0, l0, int(S.lterms.size() / 2) - l0});
         }
-        push_int(blob, S.off_slots, S.slots);
-        push_int(blob, S.off_gterms, S.gterms);
-        push_int(blob, S.off_lterms, S.lterms);
+        push_uses(S, int(P.classes.size()), blob);
     }
     {
         dgfs::SlotSet& S = P.pair_slots;
@@ -391,9 +413,7 @@ void build_tables(dgfs_plan& P, std::vector<char>& blob) {
                 S.lterms.insert(S.lterms.end(), {j, i * s + j});
                 S.slots.insert(S.slots.end(), {i, g0, int(S.gterms.size() / 2) - g0, l0, 1});
             }
-        push_int(blob, S.off_slots, S.slots);
-        push_int(blob, S.off_gterms, S.gterms);
-        push_int(blob, S.off_lterms, S.lterms);
+        push_uses(S, int(P.classes.size()), blob);
     }
 
     // ---------------- plain per-point FP64 path: per ordered pair, all M directions

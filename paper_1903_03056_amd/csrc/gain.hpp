@@ -687,6 +687,7 @@ struct RadialArgs {
     const int* slots;   // [nslots][5]
     const int* gterms;  // [..][2]
     const int* lterms;  // [..][2]
+    const int* cuses;   // [ncls][4]  (slot, F table) x 2 per class, -1 if unused
     int s, ncls, nrho, nb, nslots, K2;
 };
 
@@ -815,6 +816,142 @@ __global__ __launch_bounds__(256) void radial_kernel(RadialArgs<T> a) {
     }
 }
 
+// VSS radial sum with every slot of NB nodes in one thread: per class (one direction)
+// and radial point the two table values of each of its (at most two) uses are loaded
+// once and applied to the NB nodes' partials, which are each read once.  The per-slot
+// accumulators are indexed with compile-time slots (SMAX >= nslots) under uniform
+// compares, so they stay in registers.  Loss terms and outputs as in radial_kernel.
+template <typename T, int N, int CH, int NB, int SMAX>
+__global__ __launch_bounds__(256) void radial_vss_kernel(RadialArgs<T> a) {
+    constexpr int NP = N / CH;
+    constexpr int KZH = N / 2 + 1;
+    constexpr int64_t N2 = int64_t(N) * N, N3 = N2 * N, PCH = int64_t(NP) * N * KZH;
+    constexpr int64_t PCHF = int64_t(NP) * N2, NREP = N2 * KZH;
+    const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t ngroups = (a.nb + NB - 1) / NB;
+    if (t >= ngroups * PCH) return;
+    const int e = int(t % PCH);
+    const int b0 = int(t / PCH) * NB;
+    const int kz = e % KZH, ky = (e / KZH) % N, kxp = e / (N * KZH);
+    const int kxpm = (NP - kxp) % NP, kym = (N - ky) % N, kzm = (N - kz) % N;
+    const int64_t eP = (int64_t(kxp) * N + ky) * N + kz, ePm = (int64_t(kxpm) * N + kym) * N + kzm;
+    const int64_t fo = (int64_t(kxp) * N + ky) * KZH + kz;
+
+    cx<double> acc[NB][SMAX][CH];
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+#pragma unroll
+        for (int sl = 0; sl < SMAX; ++sl)
+#pragma unroll
+            for (int j = 0; j < CH; ++j) acc[u][sl][j] = cx<double>{0.0, 0.0};
+
+    for (int cl = 0; cl < a.ncls; ++cl) {
+        const int s0 = a.cuses[4 * cl], s1 = a.cuses[4 * cl + 2];
+        if (s0 < 0) continue;
+        const cx<T>* F0 = a.Fv + int64_t(a.cuses[4 * cl + 1]) * a.nrho * 2 * NREP + fo;
+        const cx<T>* F1 = a.Fv + int64_t(s1 >= 0 ? a.cuses[4 * cl + 3] : a.cuses[4 * cl + 1]) * a.nrho * 2 * NREP + fo;
+        for (int q = 0; q < a.nrho; ++q) {
+            cx<T> t10[CH], t20[CH], t11[CH], t21[CH];
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int64_t o = int64_t(j) * NP * N * KZH;
+                t10[j] = F0[(int64_t(q) * 2 + 0) * NREP + o];
+                t20[j] = F0[(int64_t(q) * 2 + 1) * NREP + o];
+                t11[j] = F1[(int64_t(q) * 2 + 0) * NREP + o];
+                t21[j] = F1[(int64_t(q) * 2 + 1) * NREP + o];
+            }
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                const int b = b0 + u;
+                if (b >= a.nb) break;
+                const cx<T>* Pb = a.P + ((int64_t(b) * a.ncls + cl) * a.nrho + q) * (CH * PCHF);
+                cx<T> pc[CH], pm[CH];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    pc[c] = Pb[c * PCHF + eP];
+                    pm[c] = Pb[c * PCHF + ePm];
+                }
+#pragma unroll
+                for (int j = 0; j < CH; ++j) {
+                    const int kx = kxp + j * NP, kxm = (N - kx) % N;
+                    cx<T> Z = pc[0], Zm = pm[0];
+#pragma unroll
+                    for (int c = 1; c < CH; ++c) {
+                        cmac(Z, a.tw[kx * CH + c], pc[c]);
+                        cmac(Zm, a.tw[kxm * CH + c], pm[c]);
+                    }
+                    // (t1 Z + t2 conj Zm) / 2 for each use of the class
+                    const double zx = Z.x, zy = Z.y, mx = Zm.x, my = Zm.y;
+#pragma unroll
+                    for (int sl = 0; sl < SMAX; ++sl) {
+                        if (sl == s0) {
+                            acc[u][sl][j].x += 0.5 * (double(t10[j].x) * zx - double(t10[j].y) * zy +
+                                                      double(t20[j].x) * mx + double(t20[j].y) * my);
+                            acc[u][sl][j].y += 0.5 * (double(t10[j].x) * zy + double(t10[j].y) * zx -
+                                                      double(t20[j].x) * my + double(t20[j].y) * mx);
+                        }
+                        if (sl == s1) {
+                            acc[u][sl][j].x += 0.5 * (double(t11[j].x) * zx - double(t11[j].y) * zy +
+                                                      double(t21[j].x) * mx + double(t21[j].y) * my);
+                            acc[u][sl][j].y += 0.5 * (double(t11[j].x) * zy + double(t11[j].y) * zx -
+                                                      double(t21[j].x) * my + double(t21[j].y) * mx);
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    const bool mirror = kz != 0 && kz != N / 2;
+    const int ky2 = (N - ky) % N, kz2 = (N - kz) % N;
+    int k2[CH];
+    auto sq = [](int k) {
+        const int mk = k < N / 2 ? k : k - N;
+        return mk * mk;
+    };
+#pragma unroll
+    for (int j = 0; j < CH; ++j) k2[j] = sq(kxp + j * NP) + sq(ky) + sq(kz);
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int b = b0 + u;
+        if (b >= a.nb) break;
+#pragma unroll
+        for (int sl = 0; sl < SMAX; ++sl) {
+            if (sl >= a.nslots) break;
+            const int* sd = a.slots + 5 * sl;
+            const int l0 = sd[3], nl = sd[4];
+            cx<T> lac[CH];
+#pragma unroll
+            for (int j = 0; j < CH; ++j) lac[j] = cx<T>{T(0), T(0)};
+            for (int li = 0; li < nl; ++li) {
+                const int sj = a.lterms[2 * (l0 + li)], gt = a.lterms[2 * (l0 + li) + 1];
+                const cx<T>* fj = a.fhat + (int64_t(b) * a.s + sj) * N3 + ky * N + kz;
+#pragma unroll
+                for (int j = 0; j < CH; ++j) {
+                    const int kx = kxp + j * NP;
+                    const T gm = a.G[int64_t(gt) * a.K2 + k2[j]];
+                    const cx<T> v = fj[kx * N2];
+                    lac[j].x = fma(gm, v.x, lac[j].x);
+                    lac[j].y = fma(gm, v.y, lac[j].y);
+                }
+            }
+            const int64_t ob = (int64_t(b) * a.nslots + sl) * N3;
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int kx = kxp + j * NP;
+                const int64_t o = ob + kx * N2 + ky * N + kz;
+                a.Gt[o] = cx<T>{T(acc[u][sl][j].x), T(acc[u][sl][j].y)};
+                a.Lt[o] = lac[j];
+                if (mirror) {
+                    const int64_t o2 = ob + ((N - kx) % N) * N2 + ky2 * N + kz2;
+                    a.Gt[o2] = cx<T>{T(acc[u][sl][j].x), T(-acc[u][sl][j].y)};
+                    a.Lt[o2] = cx<T>{lac[j].x, -lac[j].y};
+                }
+            }
+        }
+    }
+}
+
 // ============================================================ combine kernel
 template <typename T>
 __global__ __launch_bounds__(256) void combine_kernel(const cx<T>* __restrict__ Gt, const cx<T>* __restrict__ Lt,
@@ -890,14 +1027,32 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
     ra.slots = reinterpret_cast<const int*>(dev + ss.off_slots);
     ra.gterms = reinterpret_cast<const int*>(dev + ss.off_gterms);
     ra.lterms = reinterpret_cast<const int*>(dev + ss.off_lterms);
+    ra.cuses = reinterpret_cast<const int*>(dev + ss.off_cuses);
     ra.s = p.s;
     ra.ncls = ncls;
     ra.nrho = p.nrho;
     ra.nb = nb;
     ra.nslots = ss.nslots;
     ra.K2 = p.K2;
-    const int64_t rthreads = int64_t(nb) * ss.nslots * (N / CH) * N * (N / 2 + 1);
-    radial_kernel<T, N, CH, VSS><<<dim3(unsigned((rthreads + 255) / 256)), dim3(256), 0, st>>>(ra);
+    const int64_t pch = int64_t(N / CH) * N * (N / 2 + 1);
+    // VSS with few slots: the fused kernel (NB nodes x every slot per thread, accumulators
+    // of NB x SMAX x CH complex doubles kept to at most 16 of them)
+    constexpr int NB2 = (2 * CH <= 4) ? 4 : (2 * CH <= 8 ? 2 : 1);
+    constexpr int NB4 = (4 * CH <= 4) ? 4 : (4 * CH <= 8 ? 2 : 1);
+    const int64_t rthreads = int64_t(nb) * ss.nslots * pch;
+    if constexpr (VSS) {
+        if (ss.nslots <= 2) {
+            const int64_t th = int64_t((nb + NB2 - 1) / NB2) * pch;
+            radial_vss_kernel<T, N, CH, NB2, 2><<<dim3(unsigned((th + 255) / 256)), dim3(256), 0, st>>>(ra);
+        } else if (ss.nslots <= 4) {
+            const int64_t th = int64_t((nb + NB4 - 1) / NB4) * pch;
+            radial_vss_kernel<T, N, CH, NB4, 4><<<dim3(unsigned((th + 255) / 256)), dim3(256), 0, st>>>(ra);
+        } else {
+            radial_kernel<T, N, CH, true><<<dim3(unsigned((rthreads + 255) / 256)), dim3(256), 0, st>>>(ra);
+        }
+    } else {
+        radial_kernel<T, N, CH, false><<<dim3(unsigned((rthreads + 255) / 256)), dim3(256), 0, st>>>(ra);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     mark(3);
 

@@ -53,7 +53,8 @@ struct PairParams {
 struct SlotSet {
     int nslots = 0;
     std::vector<int> slots, gterms, lterms;
-    size_t off_slots = 0, off_gterms = 0, off_lterms = 0;  // byte offsets in the device block
+    std::vector<int> cuses;  // per class: (slot, F table) of its first and second use, -1 if none
+    size_t off_slots = 0, off_gterms = 0, off_lterms = 0, off_cuses = 0;  // byte offsets in the device block
 };
 
 }  // namespace dgfs

@@ -1,6 +1,7 @@
 """Summarise rocprofv3 output of bench.py into short text files under profiles/.
 
     python -m paper_1903_03056_amd.rocprof_summary TRACE_DIR FETCH_DIR WRITE_DIR OUT_PREFIX
+    python -m paper_1903_03056_amd.rocprof_summary --stats TRACE_DIR OUT_MD COMMAND...
 
 TRACE_DIR holds the --kernel-trace --stats csv output, FETCH_DIR / WRITE_DIR the
 --pmc FETCH_SIZE / --pmc WRITE_SIZE csv output of `bench.py --copy-probe`.  The
@@ -95,7 +96,22 @@ def main(trace_dir, fetch_dir, write_dir, prefix, command):
             json.dump(rec, fh, indent=1)
 
 
+def stats_only(trace_dir, out_path, command):
+    """Kernel statistics alone (a workload without counter passes)."""
+    stats = list(csv.DictReader(open(_one(os.path.join(trace_dir, "*kernel_stats.csv")))))
+    with open(out_path, "w") as fh:
+        fh.write(f"# rocprofv3 kernel statistics\n\nCommand:\n\n```\n{command}\n```\n\n")
+        fh.write("| kernel | calls | average us | min us | max us | share % |\n|---|---|---|---|---|---|\n")
+        for r in stats:
+            fh.write(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |\n")
+
+
 if __name__ == "__main__":
+    if sys.argv[1] == "--stats":
+        # python -m paper_1903_03056_amd.rocprof_summary --stats TRACE_DIR OUT_MD COMMAND...
+        stats_only(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+        sys.exit(0)
     t, f, w, p = sys.argv[1:5]
     cmds = {
         "trace": "rocprofv3 --kernel-trace --stats -d DIR -o trace --output-format csv -- "
