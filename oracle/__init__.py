@@ -21,5 +21,8 @@ Galerkin fast spectral method for the multi-species Boltzmann equation"):
                   remark after eq. (domain) in Sec. 4 names and leaves for later).
 * ``stepping``    forward Euler and the second-order SSP Runge-Kutta scheme of Sec. 5
                   for the spatially homogeneous problem.
+* ``dg``          the nodal DG discretisation of a 1-D slab (Sec. 5): GLL points, upwind
+                  flux, diagonal mass and collision tensor, inflow and diffuse-wall
+                  boundaries (Sec. 2).
 """
-from . import params, quadrature, vss, spectral, moments, bkw, grids, stepping  # noqa: F401
+from . import params, quadrature, vss, spectral, moments, bkw, grids, stepping, dg  # noqa: F401
