@@ -16,6 +16,8 @@ Also measured, outside the timed steps (the "workloads" object):
   * VSS kernels: the slab shape with the argon-krypton VSS parameters (sigma-dependent
     kernel mode, one transform per direction);
   * SSP-RK2 time stepping of the slab (two projected operator evaluations per step);
+  * the slab as a DG solver: nodal DG transport between two diffuse walls plus the
+    projected collisions, SSP-RK2;
   * measured ceilings: a device copy (HBM) and an FMA loop (FP32 vector).
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -266,6 +268,46 @@ def vss_leg(torch, dev, calls):
     return res
 
 
+def slab_leg(torch, dev, plan, f32, w, steps, dt=2e-4):
+    """The slab workload as a DG solver (Sec. 5): 64 elements x 4 GLL nodes on [0, 1]
+    between two diffuse walls moving at -+0.3 in y (T = 1), SSP-RK2: per step two
+    collide calls, two transport passes and the projected updates.  dt keeps the
+    transport CFL number |v_x|max dt / h = 6 x 2e-4 x 64 = 0.077 below the
+    stability limit of SSP-RK2 with cubic elements (about 1/(2p+1) = 0.14)."""
+    from paper_1903_03056_amd import Slab, slab_gll
+    s = len(w["masses"])
+    xi, wq = slab_gll(4)
+    hv3 = (2 * w["L"] / w["N"]) ** 3
+    wt = torch.tensor(np.tile(wq, 64) / 64 / 2 * hv3, dtype=torch.float64, device=dev)
+
+    def mass(f):
+        return (f.double().sum(dim=(2, 3, 4)) * wt[:, None]).sum(dim=0).cpu().numpy()
+
+    slab = Slab(plan, 0.0, 1.0, 64, 4, dict(kind="wall", u=(0.0, -0.3, 0.0), T=1.0),
+                dict(kind="wall", u=(0.0, 0.3, 0.0), T=1.0))
+    f = torch.tensor(f32, device=dev)
+    ws = torch.empty(slab.workspace_bytes(), dtype=torch.uint8, device=dev)
+    m0 = mass(f)
+    slab.step(f, dt, 1, workspace=ws)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    slab.step(f, dt, steps, workspace=ws)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    m1 = mass(f)
+    ok = bool(torch.isfinite(f).all())
+    slab.close()
+    return {"workload": "DG slab: 64 elements x 4 GLL nodes on [0, 1], diffuse walls u_y = -+0.3, T = 1, "
+                        "the slab species/kernel/grid above, SSP-RK2 dt = 2e-4",
+            "ms_per_step": round(ms, 3), "steps": steps + 1,
+            "node_steps_per_s": round(w["batch"] / (ms * 1e-3), 1),
+            "operator_evals_per_s": round(2 * w["batch"] * s * s / (ms * 1e-3), 1), "finite": ok,
+            "mass_drift_between_walls": [float(abs(a / b - 1)) for a, b in zip(m1, m0)]}
+
+
 def relax_leg(torch, dev, plan, f32, w, steps, dt=0.01):
     """SSP-RK2 time stepping of the slab workload (two projected operator evaluations
     per step, all on the device), timed with events around each call."""
@@ -445,6 +487,8 @@ def main():
         checks += c
         log("VSS kernels")
         extra["vss_slab"] = vss_leg(torch, dev, 5)
+        log("DG slab")
+        extra["dg_slab"] = slab_leg(torch, dev, plan, f32, w, 10)
         log("SSP-RK2 stepping")
         extra["ssprk2_relax"], c = relax_leg(torch, dev, plan, f32, w, 10)
         checks += c

@@ -186,6 +186,55 @@ dgfs_status dgfs_relax_workspace_size(const dgfs_plan* plan, int64_t batch, int3
 dgfs_status dgfs_relax(const dgfs_plan* plan, void* f, int64_t batch, double dt, int32_t steps, int32_t scheme,
                        void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- 1-D slab: nodal discontinuous Galerkin transport around the collision operator --
+ * Sec. 5: [x0, x1] is cut into Ne equal elements with K Gauss-Lobatto-Legendre points
+ * each (interpolation and quadrature points alike, so the mass matrix and the collision
+ * tensor are diagonal); per element, node m, species i and velocity v
+ *   dF_m/dt = 2/(h w_m) [ v_x sum_l w_l D_lm F_l - (face terms) ] + P(Q(F_m)),
+ * with D_lm the derivative of the m-th Lagrange polynomial at point l and the upwind
+ * flux (eq. flux) on the faces.  Outside the slab (Sec. 2): an inflow Maxwellian
+ * (eq. bc_inlet) or a purely diffuse wall (eq. bc_wall with accommodation 1, its density
+ * n_w from eq. bc_nwall as sums over the velocity grid).  Maxwellians are the
+ * nondimensional n (m/(pi T))^{3/2} exp(-m |v - u|^2 / T) of Sec. 3.  P(Q) is the
+ * collision operator of the plan followed by the FP64 projection of dgfs_conserve. */
+enum { DGFS_BC_INFLOW = 0, DGFS_BC_WALL = 1 };
+
+typedef struct {
+    int32_t kind;      /* DGFS_BC_INFLOW or DGFS_BC_WALL */
+    double n[8];       /* inflow: number density of each species (ignored for a wall) */
+    double u[3];       /* inflow velocity, or wall velocity (its x component must be 0) */
+    double T;          /* temperature, > 0 */
+} dgfs_boundary;
+
+typedef struct {
+    double x0, x1;     /* ends of the slab, x1 > x0 */
+    int32_t Ne;        /* elements, >= 1 */
+    int32_t K;         /* GLL points per element, 2..8 */
+    dgfs_boundary left, right;
+    int32_t collide;   /* 1: transport and collisions; 0: transport only */
+} dgfs_slab_desc;
+
+typedef struct dgfs_slab dgfs_slab;
+
+/* Create a slab over `plan` (not owned; it must outlive the slab).  Its state f is the
+ * batch of Ne*K nodes of the plan, device [Ne][K][s][N^3] in the plan precision, node
+ * (e, m) at x = x0 + e h + (1 + xi_m) h/2.  Uploads small tables to the current device. */
+dgfs_status dgfs_slab_create(const dgfs_plan* plan, const dgfs_slab_desc* desc, dgfs_slab** out);
+void dgfs_slab_destroy(dgfs_slab* slab);
+
+/* Device workspace for dgfs_slab_step with `scheme` (DGFS_EULER or DGFS_SSPRK2): the
+ * stage states, Q and the collide workspace for all Ne*K nodes in one pass. */
+dgfs_status dgfs_slab_workspace_size(const dgfs_slab* slab, int32_t scheme, size_t* bytes);
+
+/* Advance f in place by `steps` steps of size dt (forward Euler, or the SSP-RK2 scheme
+ * of Sec. 5: f1 = f + dt L(f), f <- f/2 + (f1 + dt L(f1))/2).  workspace: device memory
+ * of at least dgfs_slab_workspace_size bytes, 256-byte aligned.  Asynchronous. */
+dgfs_status dgfs_slab_step(const dgfs_slab* slab, void* f, double dt, int32_t steps, int32_t scheme,
+                           void* workspace, size_t ws_bytes, void* stream);
+
+/* The slab's GLL points and weights on [-1, 1] ([K] each, host), for tests. */
+dgfs_status dgfs_slab_gll(int32_t K, double* xi, double* w);
+
 /* Host-side view of the precomputed quantities of ordered pair (i, j), for tests:
  *   info[0..5] = a, b, gamma, C_ij, R_ij, number of phase directions used;
  *   rho, w_rho: [n_rho] radial nodes and weights on [0, R_ij];

@@ -7,6 +7,8 @@ HIP kernels; this package is its thin Python binding.
 from .collision import (  # noqa: F401
     CollisionGroup,
     CollisionPlan,
+    Slab,
+    slab_gll,
     Graph,
     tile_candidates,
     check_problem,

@@ -22,7 +22,10 @@ EXPORTED = (
     "dgfs_status_string", "dgfs_last_error", "dgfs_tile_candidates", "dgfs_group_create", "dgfs_group_destroy",
     "dgfs_group_workspace_size", "dgfs_group_collide", "dgfs_group_capture", "dgfs_graph_launch",
     "dgfs_graph_destroy", "dgfs_probe_valu", "dgfs_relax_workspace_size", "dgfs_relax",
+    "dgfs_slab_create", "dgfs_slab_destroy", "dgfs_slab_workspace_size", "dgfs_slab_step", "dgfs_slab_gll",
 )
+
+DGFS_BC_INFLOW, DGFS_BC_WALL = 0, 1
 
 DGFS_EULER, DGFS_SSPRK2 = 0, 1
 
@@ -45,6 +48,15 @@ class Problem(ctypes.Structure):
         ("tile_ch", c_int32),
         ("tile_cz", c_int32),
     ]
+
+
+class Boundary(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("n", c_double * 8), ("u", c_double * 3), ("T", c_double)]
+
+
+class SlabDesc(ctypes.Structure):
+    _fields_ = [("x0", c_double), ("x1", c_double), ("Ne", c_int32), ("K", c_int32),
+                ("left", Boundary), ("right", Boundary), ("collide", c_int32)]
 
 
 class DgfsError(RuntimeError):
@@ -84,6 +96,12 @@ def load() -> ctypes.CDLL:
     lib.dgfs_probe_valu.argtypes = [c_void_p, c_size_t, c_int32, c_int32, c_void_p, POINTER(c_double)]
     lib.dgfs_relax_workspace_size.argtypes = [c_void_p, c_int64, c_int32, POINTER(c_size_t)]
     lib.dgfs_relax.argtypes = [c_void_p, c_void_p, c_int64, c_double, c_int32, c_int32, c_void_p, c_size_t, c_void_p]
+    lib.dgfs_slab_create.argtypes = [c_void_p, POINTER(SlabDesc), POINTER(c_void_p)]
+    lib.dgfs_slab_destroy.argtypes = [c_void_p]
+    lib.dgfs_slab_destroy.restype = None
+    lib.dgfs_slab_workspace_size.argtypes = [c_void_p, c_int32, POINTER(c_size_t)]
+    lib.dgfs_slab_step.argtypes = [c_void_p, c_void_p, c_double, c_int32, c_int32, c_void_p, c_size_t, c_void_p]
+    lib.dgfs_slab_gll.argtypes = [c_int32, POINTER(c_double), POINTER(c_double)]
     lib.dgfs_tile_candidates.argtypes = [c_int32, c_int32, POINTER(c_int32), c_int32, POINTER(c_int32)]
     lib.dgfs_group_create.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_void_p)]
     lib.dgfs_group_destroy.argtypes = [c_void_p]
@@ -102,7 +120,7 @@ def load() -> ctypes.CDLL:
     lib.dgfs_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         if name not in ("dgfs_plan_destroy", "dgfs_status_string", "dgfs_last_error", "dgfs_group_destroy",
-                        "dgfs_graph_destroy"):
+                        "dgfs_graph_destroy", "dgfs_slab_destroy"):
             getattr(lib, name).restype = c_int32
     _lib = lib
     return lib

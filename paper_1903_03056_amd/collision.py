@@ -378,3 +378,72 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def slab_gll(K: int):
+    """The library's GLL points and weights on [-1, 1]."""
+    lib = load()
+    x = (c_double * K)()
+    w = (c_double * K)()
+    check(lib.dgfs_slab_gll(K, x, w), "dgfs_slab_gll")
+    return np.array(x[:]), np.array(w[:])
+
+
+def _boundary(spec: dict, s: int) -> "_lib.Boundary":
+    b = _lib.Boundary()
+    b.kind = {"inflow": _lib.DGFS_BC_INFLOW, "wall": _lib.DGFS_BC_WALL}[spec["kind"]]
+    n = list(spec.get("n", ())) + [0.0] * (8 - len(spec.get("n", ())))
+    b.n = (c_double * 8)(*n[:8])
+    b.u = (c_double * 3)(*[float(x) for x in spec.get("u", (0.0, 0.0, 0.0))])
+    b.T = float(spec["T"])
+    return b
+
+
+class Slab:
+    """1-D slab of Ne elements x K GLL nodes around a CollisionPlan (dgfs_slab_*).
+    left/right: {"kind": "inflow", "n": (n_1, ..., n_s), "u": (ux, uy, uz), "T": T} or
+    {"kind": "wall", "u": (0, uy, uz), "T": T} (purely diffuse).  The state is a tensor
+    [Ne*K][s][N][N][N] of the plan's dtype, node e*K + m."""
+
+    def __init__(self, plan: "CollisionPlan", x0: float, x1: float, Ne: int, K: int, left: dict, right: dict,
+                 collide: bool = True):
+        self.plan, self.Ne, self.K = plan, Ne, K
+        self._lib = load()
+        d = _lib.SlabDesc()
+        d.x0, d.x1, d.Ne, d.K = float(x0), float(x1), int(Ne), int(K)
+        d.left, d.right = _boundary(left, plan.s), _boundary(right, plan.s)
+        d.collide = 1 if collide else 0
+        handle = c_void_p()
+        check(self._lib.dgfs_slab_create(plan._plan, ctypes.byref(d), ctypes.byref(handle)), "dgfs_slab_create")
+        self._slab = handle
+
+    def workspace_bytes(self, scheme: str = "ssprk2") -> int:
+        n = c_size_t()
+        code = {"euler": _lib.DGFS_EULER, "ssprk2": _lib.DGFS_SSPRK2}[scheme]
+        check(self._lib.dgfs_slab_workspace_size(self._slab, code, ctypes.byref(n)), "dgfs_slab_workspace_size")
+        return n.value
+
+    def step(self, f, dt: float, steps: int = 1, scheme: str = "ssprk2", workspace=None, stream=None):
+        import torch
+        if f.dim() != 5 or f.shape[0] != self.Ne * self.K:
+            raise ValueError("f must be [Ne*K][s][N][N][N]")
+        self.plan._check_f(f)
+        code = {"euler": _lib.DGFS_EULER, "ssprk2": _lib.DGFS_SSPRK2}[scheme]
+        if workspace is None:
+            workspace = torch.empty(self.workspace_bytes(scheme), dtype=torch.uint8, device=f.device)
+        st = stream if stream is not None else torch.cuda.current_stream(f.device)
+        check(self._lib.dgfs_slab_step(self._slab, c_void_p(f.data_ptr()), float(dt), int(steps), code,
+                                       c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
+                                       c_void_p(st.cuda_stream)), "dgfs_slab_step")
+        return f
+
+    def close(self):
+        if getattr(self, "_slab", None):
+            self._lib.dgfs_slab_destroy(self._slab)
+            self._slab = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

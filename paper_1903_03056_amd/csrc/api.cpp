@@ -703,6 +703,10 @@ dgfs_status run_parts(const dgfs_plan& P, const void* f, void* Q, int64_t nb, vo
 
 }  // namespace
 
+namespace dgfs {
+dgfs_status set_error(dgfs_status st, const std::string& msg) { return fail(st, msg); }
+}  // namespace dgfs
+
 size_t dgfs_plan::ws_per_node(bool pairs) const {
     if (!parts.empty()) {
         // per node, the largest part (its layout for one node, less its one-off slack)

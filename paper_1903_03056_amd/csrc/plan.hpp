@@ -118,6 +118,8 @@ hipError_t launch_move(const dgfs_plan& p, const void* in, int64_t in_stride, vo
 // out = a x + b y over n values of the plan precision.
 hipError_t launch_axpby(const dgfs_plan& p, const void* x, const void* y, void* out, double a, double b, int64_t n,
                         hipStream_t stream);
+// Record the error text returned by dgfs_last_error and return st (api.cpp).
+dgfs_status set_error(dgfs_status st, const std::string& msg);
 // Plain per-point FP64 path (plain.hip).
 size_t plain_ws_bytes(const dgfs_plan& p);
 hipError_t launch_collide_plain(const dgfs_plan& p, const double* f, double* Q, int64_t nb, void* ws,

@@ -186,3 +186,14 @@ def test_vss_loss_table_matches_oracle():
     R = OP.truncation_radius(6.0, m[0], m[1])
     ref = OS.loss_weight(np.sqrt(np.arange(3 * 16 ** 2 + 1)), R, 2 * (1 - 0.805), kern[0][1][2], 6.0, alpha=1.36)
     assert np.abs(t["loss_by_k2"] - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("K", [2, 3, 4, 5, 6, 7, 8])
+def test_slab_gll_matches_oracle(K):
+    """The library's GLL rule (bisection on P'_{K-1}) against the oracle's (numpy roots)."""
+    from oracle import dg
+    from paper_1903_03056_amd import slab_gll
+    x, w = slab_gll(K)
+    xr, wr = dg.gll(K)
+    np.testing.assert_allclose(x, xr, atol=1e-14)
+    np.testing.assert_allclose(w, wr, atol=1e-14)
