@@ -34,6 +34,8 @@ Three evaluations of the same discretised operator are provided:
   as a convolution by FFT for every (rho, sigma);
 * ``collide_pair_exact_sphere``: eq. (sum) with the sigma-integral done exactly,
   4 pi sinc(pi rho |a l - b m| / L), the M -> infinity limit of the sphere rule.
+* ``collide_pair_dealiased``: eq. (sum) with l + m = k taken literally (no wrap-around,
+  the Galerkin projection onto the kept modes), each sum a zero-padded convolution.
 """
 from __future__ import annotations
 
@@ -178,11 +180,13 @@ def _wrapped_output_modes(N, l_idx, m_idx):
     return kidx, signed_modes(N)[kidx]
 
 
-def collide_pair_direct(fi: np.ndarray, fj: np.ndarray, pr: Pair, exact_sphere: bool = False) -> np.ndarray:
+def collide_pair_direct(fi: np.ndarray, fj: np.ndarray, pr: Pair, exact_sphere: bool = False,
+                        linear: bool = False) -> np.ndarray:
     """Eq. (sum) evaluated as an explicit double sum over (l, m), O(N^6).
 
     G(l, m) = G+(l, m) - G-(m) with G+ in the (rho, sigma) quadrature form, or, when
-    ``exact_sphere`` is set, with the sigma integral done in closed form."""
+    ``exact_sphere`` is set, with the sigma integral done in closed form.  With
+    ``linear`` only pairs whose l + m lies in [-N/2, N/2-1]^3 contribute (no wrap)."""
     N = fi.shape[0]
     L = pr.L
     fhi = fourier_coefficients(fi, L).ravel()
@@ -212,6 +216,10 @@ def collide_pair_direct(fi: np.ndarray, fj: np.ndarray, pr: Pair, exact_sphere: 
                 Fqp = pr.kernel_mode(kmode, q, p)
                 Gplus += wrho[q] * pr.wsigma[p] * Fqp * np.exp(1j * np.pi * rho[q] * (d @ pr.sigma[p]) / L)
         contrib = (Gplus - Gminus) * fhi[li] * fhj
+        if linear:
+            ksum = modes[li][None, :] + modes
+            keep = np.all((ksum >= -(N // 2)) & (ksum <= N // 2 - 1), axis=1)
+            contrib = np.where(keep, contrib, 0.0)
         np.add.at(Qhat, kflat, contrib)
     return synthesize(Qhat.reshape(N, N, N), L).real
 
@@ -275,6 +283,58 @@ def collide_pair_fast(fi: np.ndarray, fj: np.ndarray, pr: Pair) -> np.ndarray:
     return _synthesize_fft(Qplus - Qminus).real
 
 
+def _pad(X: np.ndarray, P: int) -> np.ndarray:
+    """Coefficients indexed by DFT index on the N grid, placed at the same modes of a
+    P grid (P >= N); every other mode zero."""
+    N = X.shape[0]
+    idx = np.arange(N)
+    k = np.where(idx < N // 2, idx, idx - N) % P
+    out = np.zeros((P, P, P), dtype=np.complex128)
+    out[np.ix_(k, k, k)] = X
+    return out
+
+
+def _truncate(Y: np.ndarray, N: int) -> np.ndarray:
+    """Modes -N/2..N/2-1 of a P-grid array, by N-grid DFT index."""
+    P = Y.shape[0]
+    idx = np.arange(N)
+    k = np.where(idx < N // 2, idx, idx - N) % P
+    return Y[np.ix_(k, k, k)]
+
+
+def linear_convolution(X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """sum_{l+m = k} X_l Y_m over l, m, k in [-N/2, N/2-1]^3 without wrap-around: both
+    are zero-padded to a 2N grid, where l + m (in [-N, N-2]) never wraps onto a kept k."""
+    N = X.shape[0]
+    return _truncate(circular_convolution(_pad(X, 2 * N), _pad(Y, 2 * N)), N)
+
+
+def collide_pair_dealiased(fi: np.ndarray, fj: np.ndarray, pr: Pair) -> np.ndarray:
+    """Eq. (sum) read literally: the sums over l + m = k with l, m, k all in
+    [-N/2, N/2-1]^3 (no wrap-around), in the quadrature form of Sec. 4 for the gain, each
+    inner sum a linear convolution; the operator at a grid point is the real part of the
+    synthesised series, as for the circular form."""
+    N = fi.shape[0]
+    L = pr.L
+    fhi = _coefficients_fft(fi)
+    fhj = _coefficients_fft(fj)
+    KX, KY, KZ = mode_grids(N)
+    kabs = np.sqrt(KX ** 2 + KY ** 2 + KZ ** 2)
+    kvec = np.stack([KX, KY, KZ], axis=-1)
+    Qplus = np.zeros((N, N, N), dtype=np.complex128)
+    for q in range(len(pr.rho)):
+        rho = pr.rho[q]
+        for p in range(len(pr.wsigma)):
+            Fqp = pr.kernel_mode(kvec, q, p)
+            s = pr.sigma[p]
+            ksig = KX * s[0] + KY * s[1] + KZ * s[2]
+            X = np.exp(1j * np.pi * rho * pr.a * ksig / L) * fhi
+            Y = np.exp(-1j * np.pi * rho * pr.b * ksig / L) * fhj
+            Qplus += pr.wrho[q] * pr.wsigma[p] * Fqp * linear_convolution(X, Y)
+    Qminus = linear_convolution(fhi, pr.loss(kabs) * fhj)
+    return _synthesize_fft(Qplus - Qminus).real
+
+
 def collide_pair_fast_parts(fi: np.ndarray, fj: np.ndarray, pr: Pair):
     """Gain and loss of ``collide_pair_fast`` separately (real parts on the grid)."""
     N = fi.shape[0]
@@ -329,7 +389,8 @@ def vhs_problem(masses, omega: float, L: float, N: int, M: int, nrho: int, kn0: 
 def collide_pairs(f: np.ndarray, prob: Problem, method: str = "fast") -> np.ndarray:
     """Q^{ij}(f^i, f^j) for every ordered pair: f [s][N][N][N] -> [s][s][N][N][N]."""
     fn = {"fast": collide_pair_fast, "direct": collide_pair_direct,
-          "exact_sphere": collide_pair_exact_sphere}[method]
+          "exact_sphere": collide_pair_exact_sphere, "dealiased": collide_pair_dealiased,
+          "direct_linear": lambda a, b, pr: collide_pair_direct(a, b, pr, linear=True)}[method]
     s = prob.s
     out = np.zeros((s, s) + f.shape[1:])
     for i in range(s):
