@@ -99,6 +99,11 @@ typedef struct {
                                         groups per y/z pencil; 0, 0 = the library's default
                                         for (N, precision); other values must be one of
                                         dgfs_tile_candidates (DGFS_EUNSUPPORTED otherwise) */
+    int32_t dealias;                 /* 0: eq. (sum) as the circular convolution the FFT
+                                        evaluation computes on the N^3 grid; 1: l + m = k
+                                        taken literally (no wrap-around), evaluated with
+                                        spectra zero-padded to 3N/2.  1 needs N = 16 or 32,
+                                        alpha = 1, one common grid and the default tile. */
 } dgfs_problem;
 
 typedef struct dgfs_plan dgfs_plan;
@@ -143,7 +148,8 @@ dgfs_status dgfs_collide_pairs(const dgfs_plan* plan, const void* f, void* Q, in
  * pair, radial point and all M directions: phase multiply, inverse 3-D FFTs, product
  * accumulation; per radial point a forward FFT and the radial weighting; then the loss
  * convolution), without the class sharing of the antipodal designs.  Needs an FP64 plan
- * on one common grid with alpha = 1 for every pair (DGFS_EUNSUPPORTED otherwise).
+ * on one common grid with alpha = 1 for every pair, circular form (DGFS_EUNSUPPORTED
+ * otherwise).
  * f, Q: device doubles [batch][s][N^3];
  * ws_bytes >= dgfs_workspace_size(plan, 1). */
 dgfs_status dgfs_collide_plain(const dgfs_plan* plan, const double* f, double* Q, int64_t batch,

@@ -47,6 +47,7 @@ class Problem(ctypes.Structure):
         ("precision", c_int32),
         ("tile_ch", c_int32),
         ("tile_cz", c_int32),
+        ("dealias", c_int32),
     ]
 
 

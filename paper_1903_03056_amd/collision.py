@@ -33,7 +33,7 @@ def _precision_code(precision) -> int:
 class _ProblemHolder:
     """Keeps the ctypes arrays alive as long as the Problem struct refers to them."""
 
-    def __init__(self, masses, L, N, M, n_rho, kernel, precision, L_species=None, tile=None):
+    def __init__(self, masses, L, N, M, n_rho, kernel, precision, L_species=None, tile=None, dealias=False):
         s = len(masses)
         self.mass = (c_double * s)(*masses)
         self.kern = (PairKernel * (s * s))()
@@ -45,7 +45,8 @@ class _ProblemHolder:
         self.problem = Problem(s=s, mass=self.mass, L=float(L),
                                L_species=self.Ls if self.Ls is not None else None,
                                N=N, M=M, n_rho=n_rho, kernel=self.kern, precision=_precision_code(precision),
-                               tile_ch=int(tile[0]) if tile else 0, tile_cz=int(tile[1]) if tile else 0)
+                               tile_ch=int(tile[0]) if tile else 0, tile_cz=int(tile[1]) if tile else 0,
+                               dealias=1 if dealias else 0)
 
 
 def vhs_kernel(masses, omega, alpha: float = 1.0, kn0: float = 1.0):
@@ -64,9 +65,10 @@ def vss_kernel(masses, omega, alpha, kn0: float = 1.0):
              for j in range(s)] for i in range(s)]
 
 
-def check_problem(masses, L, N, M, n_rho, kernel, precision="f32", L_species=None, tile=None) -> int:
+def check_problem(masses, L, N, M, n_rho, kernel, precision="f32", L_species=None, tile=None,
+                  dealias=False) -> int:
     """Host-side validation; returns the dgfs status code (0 = ok)."""
-    h = _ProblemHolder(masses, L, N, M, n_rho, kernel, precision, L_species, tile=tile)
+    h = _ProblemHolder(masses, L, N, M, n_rho, kernel, precision, L_species, tile=tile, dealias=dealias)
     return load().dgfs_check_problem(ctypes.byref(h.problem))
 
 
@@ -123,10 +125,12 @@ class CollisionPlan:
     """A precomputed collision problem on the current HIP device.
 
     kernel[i][j] = (omega, alpha, prefactor); default: VHS with ``omega`` and the
-    prefactor of eqs. (Kn)/(NVSS) with Kn0 = ``kn0``."""
+    prefactor of eqs. (Kn)/(NVSS) with Kn0 = ``kn0``.  dealias=True evaluates eq. (sum)
+    with l + m = k literally (no wrap-around; N = 16 or 32)."""
 
     def __init__(self, masses, N: int, L, M: int, n_rho: int, omega: float | None = None,
-                 kernel=None, precision="f32", kn0: float = 1.0, tile=None, alpha: float = 1.0):
+                 kernel=None, precision="f32", kn0: float = 1.0, tile=None, alpha: float = 1.0,
+                 dealias: bool = False):
         import torch  # noqa: F401  (initialises the HIP runtime the library shares)
 
         if kernel is None:
@@ -145,7 +149,9 @@ class CollisionPlan:
             tile = best_tile(self.masses, N, self.L, M, n_rho, kernel, precision)
         self.tile = tuple(tile) if tile else None
         Lsp = self.L_species if len(set(self.L_species)) > 1 else None
-        self._holder = _ProblemHolder(self.masses, self.L, N, M, n_rho, kernel, precision, Lsp, tile=self.tile)
+        self.dealias = bool(dealias)
+        self._holder = _ProblemHolder(self.masses, self.L, N, M, n_rho, kernel, precision, Lsp, tile=self.tile,
+                                      dealias=self.dealias)
         self._lib = load()
         handle = c_void_p()
         check(self._lib.dgfs_plan_create(ctypes.byref(self._holder.problem), ctypes.byref(handle)),

@@ -57,6 +57,17 @@ dgfs_status check(const dgfs_problem* p) {
                 return fail(DGFS_EINVAL, "kernel must be symmetric in (i, j)");
         }
     if (!n_supported(p->N)) return fail(DGFS_EUNSUPPORTED, "N must be 16, 24, 32 or 48");
+    if (p->dealias != 0 && p->dealias != 1) return fail(DGFS_EINVAL, "dealias must be 0 or 1");
+    if (p->dealias) {
+        if (p->N != 16 && p->N != 32) return fail(DGFS_EUNSUPPORTED, "the dealiased form needs N = 16 or 32");
+        for (int i = 0; i < p->s * p->s; ++i)
+            if (p->kernel[i].alpha != 1.0) return fail(DGFS_EUNSUPPORTED, "the dealiased form needs alpha = 1");
+        if (p->L_species)
+            for (int i = 1; i < p->s; ++i)
+                if (p->L_species[i] != p->L_species[0])
+                    return fail(DGFS_EUNSUPPORTED, "the dealiased form needs one common grid");
+        if (p->tile_ch != 0 || p->tile_cz != 0) return fail(DGFS_EUNSUPPORTED, "the dealiased form uses the default tile");
+    }
     dgfs::GainGeometry g;
     if (!dgfs::gain_geometry(p->N, p->precision, &g))
         return fail(DGFS_EUNSUPPORTED, "no kernel for this N at this precision");
@@ -722,6 +733,8 @@ size_t dgfs_plan::ws_per_node(bool pairs) const {
     // spectrum of the complex field S_0 + i S_1
     const size_t part = vss ? 2 * elem() * n3() : 2 * elem() * size_t(N) * N * (N / 2 + 1);
     const int nslots = pairs ? s * s : s;
+    if (inner)
+        return dgfs::dealias_ws_per_node(elem(), N, s, int(inner->classes.size()), inner->nrho, nslots);
     return c * (size_t(s) + 2 * size_t(nslots)) + part * classes.size() * size_t(nrho);
 }
 
@@ -777,12 +790,52 @@ dgfs_status dgfs_plan_create(const dgfs_problem* problem, dgfs_plan** out) {
         single.L = problem->L_species[0];
         single.L_species = nullptr;
     }
-    return create_single(&single, std::vector<unsigned char>(size_t(problem->s) * problem->s, 1), out);
+    const std::vector<unsigned char> all(size_t(problem->s) * problem->s, 1);
+    if (!problem->dealias) return create_single(&single, all, out);
+    // dealiased: this plan keeps the N-grid conservation tables; its companion on the
+    // 3N/2 grid holds the tables of the padded gain and loss
+    single.dealias = 0;
+    dgfs_plan* outer = nullptr;
+    if ((st = create_single(&single, all, &outer)) != DGFS_OK) return st;
+    dgfs_problem wide = single;
+    wide.N = 3 * problem->N / 2;
+    if ((st = create_single(&wide, all, &outer->inner)) != DGFS_OK) {
+        dgfs_plan_destroy(outer);
+        return st;
+    }
+    // sub-classes over the split fields H_i (index i) and K_i (index s + i) of the padded
+    // spectrum P = H + i K: HH (weight w), KK (weight -w), HK and KH (weight w, their
+    // partials multiplied by i when combined)
+    const dgfs_plan& in = *outer->inner;
+    const int nc = int(in.classes.size()), s = in.s;
+    std::vector<int> cls4;
+    std::vector<double> w4;
+    for (int v = 0; v < 4; ++v)
+        for (const auto& c : in.classes) {
+            const int fi = (v == 1 || v == 3) ? s + c.i : c.i;
+            const int fj = (v == 1 || v == 2) ? s + c.j : c.j;
+            cls4.insert(cls4.end(), {fi, fj, c.ndir, c.dir_offset});
+            w4.push_back(v == 1 ? -c.weight : c.weight);
+        }
+    std::vector<char> blob;
+    push_int(blob, outer->off_cls4, cls4);
+    if (outer->precision == DGFS_FP64) push_real<double>(blob, outer->off_w4, w4);
+    else push_real<float>(blob, outer->off_w4, w4);
+    (void)nc;
+    if (hipMalloc(&outer->dealias_dev, blob.size()) != hipSuccess ||
+        hipMemcpy(outer->dealias_dev, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        dgfs_plan_destroy(outer);
+        return fail(DGFS_ENOMEM, "upload of the dealiasing tables failed");
+    }
+    *out = outer;
+    return DGFS_OK;
 }
 
 void dgfs_plan_destroy(dgfs_plan* plan) {
     if (!plan) return;
     for (auto& part : plan->parts) dgfs_plan_destroy(part.plan);
+    if (plan->inner) dgfs_plan_destroy(plan->inner);
+    if (plan->dealias_dev) hipFree(plan->dealias_dev);
     if (plan->dev) hipFree(plan->dev);
     delete plan;
 }
@@ -872,6 +925,7 @@ dgfs_status dgfs_collide_plain(const dgfs_plan* plan, const double* f, double* Q
     if (plan->precision != DGFS_FP64) return fail(DGFS_EUNSUPPORTED, "the plain path needs an FP64 plan");
     if (!plan->parts.empty()) return fail(DGFS_EUNSUPPORTED, "the plain path has one common grid");
     if (plan->vss) return fail(DGFS_EUNSUPPORTED, "the plain path covers the VHS family (alpha = 1)");
+    if (plan->inner) return fail(DGFS_EUNSUPPORTED, "the plain path evaluates the circular form");
     if (batch < 0) return fail(DGFS_EINVAL, "batch must be >= 0");
     if (batch == 0) return DGFS_OK;
     if (!f || !Q || !workspace) return fail(DGFS_EINVAL, "f, Q and workspace are required");

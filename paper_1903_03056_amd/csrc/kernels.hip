@@ -144,6 +144,13 @@ bool gain_geometry(int N, int precision, GainGeometry* g) { return tile_candidat
 
 hipError_t launch_collide(const dgfs_plan& p, const void* f, void* Q, int64_t nb, void* ws, bool pairs,
                           hipStream_t st, hipEvent_t* ev) {
+    if (p.inner) {
+        switch (p.N) {
+            case 16: return run_dealias_16(p, *p.inner, f, Q, int(nb), ws, pairs, st, ev);
+            case 32: return run_dealias_32(p, *p.inner, f, Q, int(nb), ws, pairs, st, ev);
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (p.vss) {
         switch (p.N) {
             case 16: return run_vss_16(p, f, Q, int(nb), ws, pairs, st, ev);

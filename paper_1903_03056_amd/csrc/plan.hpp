@@ -95,6 +95,14 @@ struct dgfs_plan {
     };
     std::vector<GridPart> parts;
 
+    // Dealiased form (linear convolution): the companion plan on the 3N/2 grid whose
+    // tables the padded gain and loss use; this plan keeps the conservation tables.
+    dgfs_plan* inner = nullptr;
+    // ... and the four sub-classes of each inner class over the split fields (below):
+    // [4][ncls][4] ints (i, j, ndir, dir_offset) then [4][ncls] weights (plan precision)
+    void* dealias_dev = nullptr;
+    size_t off_cls4 = 0, off_w4 = 0;
+
     size_t elem() const { return precision == DGFS_FP64 ? sizeof(double) : sizeof(float); }
     size_t n3() const { return size_t(N) * N * N; }
     // workspace bytes per node, and the alignment slack added once per call
@@ -107,6 +115,11 @@ namespace dgfs {
 // ev: NULL, or 6 events recorded at the stage boundaries of the slice.
 hipError_t launch_collide(const dgfs_plan& p, const void* f, void* Q, int64_t nb, void* ws,
                           bool pairs, hipStream_t stream, hipEvent_t* ev);
+// The dealiased pipeline (vss_24.hip: N = 16, vss_48.hip: N = 32).
+hipError_t run_dealias_16(const dgfs_plan& outer, const dgfs_plan& inner, const void* f, void* Q, int nb, void* ws,
+                          bool pairs, hipStream_t st, hipEvent_t* ev);
+hipError_t run_dealias_32(const dgfs_plan& outer, const dgfs_plan& inner, const void* f, void* Q, int nb, void* ws,
+                          bool pairs, hipStream_t st, hipEvent_t* ev);
 // out != NULL: out = projection of Q (FP64); fstate != NULL: fstate += dt * projection.
 hipError_t launch_conserve(const dgfs_plan& p, const void* Q, double* out, void* fstate, double dt, int64_t nb,
                            hipStream_t stream);
@@ -118,6 +131,14 @@ hipError_t launch_move(const dgfs_plan& p, const void* in, int64_t in_stride, vo
 // out = a x + b y over n values of the plan precision.
 hipError_t launch_axpby(const dgfs_plan& p, const void* x, const void* y, void* out, double a, double b, int64_t n,
                         hipStream_t stream);
+// Workspace bytes per node of the dealiased pipeline on an N-grid plan (NI = 3N/2):
+// f_hat on N, f_hat, its two Hermitian parts and the complex interpolant on NI, the
+// partials of the four sub-classes on NI, the loss spectra on NI and the kept modes on N.
+inline size_t dealias_ws_per_node(size_t elem, int N, int s, int ncls, int nrho, int nslots) {
+    const size_t c = 2 * elem, N3 = size_t(N) * N * N, NI = size_t(3 * N / 2), NI3 = NI * NI * NI;
+    return c * (size_t(s) * N3 + 4 * size_t(s) * NI3 + 4 * size_t(ncls) * nrho * NI3 + size_t(nslots) * NI3 +
+                size_t(nslots) * N3) + 7 * 256;
+}
 // Record the error text returned by dgfs_last_error and return st (api.cpp).
 dgfs_status set_error(dgfs_status st, const std::string& msg);
 // Plain per-point FP64 path (plain.hip).

@@ -197,3 +197,17 @@ def test_slab_gll_matches_oracle(K):
     xr, wr = dg.gll(K)
     np.testing.assert_allclose(x, xr, atol=1e-14)
     np.testing.assert_allclose(w, wr, atol=1e-14)
+
+
+def test_check_problem_dealias():
+    from paper_1903_03056_amd import check_problem
+    from paper_1903_03056_amd._lib import DGFS_EUNSUPPORTED, DGFS_OK
+    m = (1.0, 2.0)
+    k = _kern(m, 0.74)
+    assert check_problem(m, 6.0, 16, 6, 8, k, dealias=True) == DGFS_OK
+    assert check_problem(m, 6.0, 32, 12, 16, k, dealias=True) == DGFS_OK
+    assert check_problem(m, 6.0, 24, 12, 12, k, dealias=True) == DGFS_EUNSUPPORTED    # 36 not compiled
+    vss = [[(0.74, 1.4, 1.0)] * 2 for _ in range(2)]
+    assert check_problem(m, 6.0, 16, 6, 8, vss, dealias=True) == DGFS_EUNSUPPORTED
+    assert check_problem(m, 6.0, 16, 6, 8, k, L_species=(6.0, 3.0), dealias=True) == DGFS_EUNSUPPORTED
+    assert check_problem(m, 6.0, 16, 6, 8, k, tile=(2, 1), dealias=True) == DGFS_EUNSUPPORTED
