@@ -256,6 +256,14 @@ def vss_leg(torch, dev, calls):
     ms_call = e0.elapsed_time(e1) / calls
     stage /= calls
     flops = w["batch"] * gain_flops_per_node_vss(w["N"], w["M"], w["n_rho"], s)
+    # radial stage bytes: each direction's whole-spectrum partial read once per node, the
+    # two complex tables of each (direction, target) use once per group of 4 nodes, the
+    # gain and loss spectra written, the loss terms' f_hat read
+    N3, NREP = w["N"] ** 3, w["N"] * w["N"] * (w["N"] // 2 + 1)
+    dirs = s * (w["M"] // 2) + (s * (s - 1) // 2) * w["M"]
+    uses = s * (w["M"] // 2) + s * (s - 1) * w["M"]
+    radial_bytes = w["batch"] * (dirs * w["n_rho"] * N3 * 8 + uses * w["n_rho"] * 2 * NREP * 8 / 4
+                                 + 2 * s * N3 * 8 + s * s * N3 * 8)
     res = {"workload": "VSS slab: 256 nodes, argon-krypton VSS kernels (omega 0.81/0.805/0.8, alpha "
                        "1.4/1.36/1.32, m2/m1 = 2.098), N=32, L=6, M=12, N_rho=16, bi-Maxwellian + 1e-2 noise, "
                        "seed 2, FP32",
@@ -265,6 +273,15 @@ def vss_leg(torch, dev, calls):
                          "radial_loss": round(stage[2], 4), "inverse_fft": round(stage[3], 4),
                          "combine": round(stage[4], 4)},
            "gain_tflops": round(flops / (stage[1] * 1e-3) / 1e12, 2),
+           "roofline": {
+               "gain": {"bound": "alu", "achieved": round(flops / (stage[1] * 1e-3) / 1e12, 3),
+                        "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(flops / (stage[1] * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4),
+                        "flop_per_launch": flops},
+               "radial": {"bound": "hbm", "achieved": round(radial_bytes / (stage[2] * 1e-3) / 1e9, 1),
+                          "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                          "frac": round(radial_bytes / (stage[2] * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
+                          "bytes_per_launch": radial_bytes}},
            "setup_s": round(setup_s, 2)}
     return res
 
@@ -307,12 +324,32 @@ def slab_leg(torch, dev, plan, w, steps, dt=2e-4):
     m1 = mass(f)
     ok = bool(torch.isfinite(f).all())
     slab.close()
+    # transport alone (collisions off): per SSP-RK2 step two transport passes (each reads
+    # the state plus two face traces per element and writes the stage state), two wall
+    # reductions and the averaging pass (two reads, one write)
+    tslab = Slab(plan, 0.0, 1.0, 64, 4, dict(kind="wall", u=(0.0, -0.3, 0.0), T=1.0),
+                 dict(kind="wall", u=(0.0, 0.3, 0.0), T=1.0), collide=False)
+    tws = torch.empty(tslab.workspace_bytes(), dtype=torch.uint8, device=dev)
+    tslab.step(f, dt, 1, workspace=tws)
+    e0.record(st)
+    tslab.step(f, dt, 20, workspace=tws)
+    e1.record(st)
+    torch.cuda.synchronize()
+    tms = e0.elapsed_time(e1) / 20
+    tslab.close()
+    sb = w["batch"] * s * w["N"] ** 3 * 4
+    tbytes = 2 * (sb * (1 + 2 / 4) + sb) + 3 * sb
     return {"workload": "DG slab: 64 elements x 4 GLL nodes on [0, 1], diffuse walls u_y = -+0.3, T = 1, "
                         "the slab species/kernel/grid above, noise-free bi-Maxwellians, SSP-RK2 dt = 2e-4",
             "ms_per_step": round(ms, 3), "steps": steps + 1,
             "node_steps_per_s": round(w["batch"] / (ms * 1e-3), 1),
             "operator_evals_per_s": round(2 * w["batch"] * s * s / (ms * 1e-3), 1), "finite": ok,
-            "mass_drift_between_walls": [float(abs(a / b - 1)) for a, b in zip(m1, m0)]}
+            "mass_drift_between_walls": [float(abs(a / b - 1)) for a, b in zip(m1, m0)],
+            "transport_only_ms_per_step": round(tms, 4),
+            "transport_roofline": {"bound": "hbm", "achieved": round(tbytes / (tms * 1e-3) / 1e9, 1),
+                                   "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                                   "frac": round(tbytes / (tms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
+                                   "bytes_per_step": tbytes}}
 
 
 def dealias_leg(torch, dev, f32, w, calls):
@@ -338,7 +375,14 @@ def dealias_leg(torch, dev, f32, w, calls):
     torch.cuda.synchronize()
     ms_call = e0.elapsed_time(e1) / calls
     stage /= calls
-    return {"workload": "the slab workload (256 nodes, N=32, M=12, N_rho=16, FP32) with the linear (dealiased) "
+    NI = 3 * w["N"] // 2
+    flops = w["batch"] * gain_flops_per_node_vss(NI, w["M"], w["n_rho"], s)
+    return {"roofline_gain": {"bound": "alu", "achieved": round(flops / (stage[1] * 1e-3) / 1e12, 3),
+                              "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                              "frac": round(flops / (stage[1] * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4),
+                              "flop_model": "the padded gain as one complex product per direction on 48^3 "
+                                            "(the four Hermitian sub-classes are overhead, not counted)"},
+            "workload": "the slab workload (256 nodes, N=32, M=12, N_rho=16, FP32) with the linear (dealiased) "
                         "convolution, padded to 48^3, 64-node workspace slices",
             "value": round(w["batch"] * s * s / (ms_call * 1e-3), 1), "unit": "evals/s", "calls": calls,
             "ms_per_call": round(ms_call, 3),
@@ -382,7 +426,7 @@ def main():
                     help="leave out the plain per-point FP64 comparison leg (not part of the timed step)")
     ap.add_argument("--no-extra", action="store_true",
                     help="leave out the uneven-batch, species-grid, SSP-RK2 and measured-ceiling legs")
-    ap.add_argument("--only-leg", choices=["vss_slab"], default=None,
+    ap.add_argument("--only-leg", choices=["vss_slab", "dg_slab", "dealiased_slab"], default=None,
                     help="run only the named extra workload and print its JSON (for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain device copy of 2 x 256 MiB first (calibrates HBM byte counters)")
@@ -401,6 +445,18 @@ def main():
     if args.only_leg == "vss_slab":
         log("VSS kernels only")
         print(json.dumps({"vss_slab": vss_leg(torch, torch.device("cuda:0"), args.steps)}), flush=True)
+        return
+    if args.only_leg in ("dg_slab", "dealiased_slab"):
+        w = WORKLOAD
+        dev = torch.device("cuda:0")
+        if args.only_leg == "dg_slab":
+            plan = CollisionPlan(w["masses"], w["N"], w["L"], w["M"], w["n_rho"], omega=w["omega"], precision="f32")
+            res = slab_leg(torch, dev, plan, w, args.steps)
+        else:
+            f32 = I.draw_bimaxwellian_batch(np.random.default_rng(w["seed"]), w["batch"], len(w["masses"]), w["N"],
+                                            w["L"], w["masses"], noise=w["noise"]).astype(np.float32)
+            res = dealias_leg(torch, dev, f32, w, args.steps)
+        print(json.dumps({args.only_leg: res}), flush=True)
         return
 
     w = WORKLOAD

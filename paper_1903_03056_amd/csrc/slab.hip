@@ -103,21 +103,25 @@ std::vector<double> lagrange_diff(const std::vector<double>& x) {
 double maxwellian_1d(double v, double m, double u, double T) { return std::exp(-m * (v - u) * (v - u) / T); }
 
 // ------------------------------------------------------------------- kernels
-// Per side and species: n_w = -sum_{vx n >= 0} (vx n) f_trace / den  (den holds the
-// matching sum over the incoming half for the unit wall Maxwellian, precomputed).
-template <typename T>
+constexpr int kWallBlocks = 64;  // blocks per (wall, species) of the wall reduction
+
+// Per side and species, partial sums over a slice of the velocity grid of
+// -sum_{vx n >= 0} (vx n) f_trace; the transport kernel adds the kWallBlocks partials and
+// divides by den (the matching sum over the incoming half for the unit wall Maxwellian,
+// precomputed) to get n_w.
+template <typename T, int N>
 __global__ __launch_bounds__(256) void wall_density_kernel(const T* __restrict__ f, const T* __restrict__ vx,
-                                                           const double* __restrict__ den, double* __restrict__ nw,
-                                                           int s, int N, int64_t left_node, int64_t right_node,
-                                                           int left_wall, int right_wall) {
-    const int side = blockIdx.x / s, i = blockIdx.x % s;
+                                                           double* __restrict__ part, int s, int64_t left_node,
+                                                           int64_t right_node, int left_wall, int right_wall) {
+    constexpr int N3 = N * N * N, SLICE = N3 / kWallBlocks;
+    const int blk = blockIdx.x % kWallBlocks, si = blockIdx.x / kWallBlocks;
+    const int side = si / s, i = si % s;
     if ((side == 0 && !left_wall) || (side == 1 && !right_wall)) return;
-    const int64_t n3 = int64_t(N) * N * N;
-    const T* tr = f + ((side == 0 ? left_node : right_node) * s + i) * n3;
+    const T* tr = f + ((side == 0 ? left_node : right_node) * s + i) * int64_t(N3);
     const double normal = side == 0 ? -1.0 : 1.0;
     double acc = 0.0;
-    for (int64_t v = threadIdx.x; v < n3; v += 256) {
-        const double vn = double(vx[i * N + int(v / (int64_t(N) * N))]) * normal;
+    for (int v = blk * SLICE + threadIdx.x; v < (blk + 1) * SLICE; v += 256) {
+        const double vn = double(vx[i * N + v / (N * N)]) * normal;
         if (vn >= 0.0) acc += vn * double(tr[v]);
     }
     __shared__ double red[256];
@@ -127,41 +131,48 @@ __global__ __launch_bounds__(256) void wall_density_kernel(const T* __restrict__
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) nw[side * s + i] = -red[0] / den[side * s + i];
+    if (threadIdx.x == 0) part[(side * s + i) * kWallBlocks + blk] = -red[0];
 }
 
 struct TransportArgs {
     const double* coef;  // [K][K] c_lm = w_l D_lm, then [K] 2/(h w_m)
     const void* vx;      // [s][N]
     const void* bt;      // [2][s][N^3]  inflow state, or unit wall Maxwellian
-    const double* nw;    // [2][s]       wall densities (wall sides)
-    int Ne, K, s, N, left_wall, right_wall;
+    const double* den;   // [2][s]       wall denominators
+    const double* part;  // [2][s][kWallBlocks] wall numerator partials
+    int Ne, K, s, left_wall, right_wall;
     double dt;
 };
 
 // out = in + dt T(in) for every node: one thread per (element, species, velocity) holds
 // the element's K values and its two neighbour traces.
-template <typename T>
+template <typename T, int N>
 __global__ __launch_bounds__(256) void transport_kernel(const T* __restrict__ in, T* __restrict__ out, TransportArgs a) {
-    const int64_t n3 = int64_t(a.N) * a.N * a.N;
+    constexpr int N3 = N * N * N;
     const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (t >= int64_t(a.Ne) * a.s * n3) return;
-    const int64_t v = t % n3;
-    const int i = int((t / n3) % a.s);
-    const int e = int(t / (n3 * a.s));
+    if (t >= int64_t(a.Ne) * a.s * N3) return;
+    const int v = int(t % N3);
+    const int es = int(t / N3);
+    const int i = es % a.s, e = es / a.s;
     const int K = a.K;
     const T* vxt = static_cast<const T*>(a.vx);
     const T* bt = static_cast<const T*>(a.bt);
-    const T vx = vxt[i * a.N + int(v / (int64_t(a.N) * a.N))];
-    auto at = [&](int ee, int m) { return in[((int64_t(ee) * K + m) * a.s + i) * n3 + v]; };
+    const T vx = vxt[i * N + v / (N * N)];
+    auto at = [&](int ee, int m) { return in[((int64_t(ee) * K + m) * a.s + i) * N3 + v]; };
+    auto wall_density = [&](int side) {
+        double num = 0.0;
+        const double* pp = a.part + (side * a.s + i) * kWallBlocks;
+        for (int k = 0; k < kWallBlocks; ++k) num += pp[k];
+        return T(num / a.den[side * a.s + i]);
+    };
     T F[kMaxK];
     for (int m = 0; m < K; ++m) F[m] = at(e, m);
     // outside values at the two faces (only used for incoming velocities)
     T outl, outr;
     if (e > 0) outl = at(e - 1, K - 1);
-    else outl = bt[(0 * a.s + i) * n3 + v] * (a.left_wall ? T(a.nw[0 * a.s + i]) : T(1));
+    else outl = bt[(0 * a.s + i) * int64_t(N3) + v] * (a.left_wall ? wall_density(0) : T(1));
     if (e < a.Ne - 1) outr = at(e + 1, 0);
-    else outr = bt[(1 * a.s + i) * n3 + v] * (a.right_wall ? T(a.nw[1 * a.s + i]) : T(1));
+    else outr = bt[(1 * a.s + i) * int64_t(N3) + v] * (a.right_wall ? wall_density(1) : T(1));
     const T fl = vx <= T(0) ? F[0] : outl;        // left face, normal -1
     const T fr = vx >= T(0) ? F[K - 1] : outr;    // right face, normal +1
     for (int m = 0; m < K; ++m) {
@@ -170,19 +181,17 @@ __global__ __launch_bounds__(256) void transport_kernel(const T* __restrict__ in
         T r = vx * vol;
         if (m == K - 1) r -= vx * fr;
         if (m == 0) r += vx * fl;
-        out[((int64_t(e) * K + m) * a.s + i) * n3 + v] = F[m] + T(a.dt) * T(a.coef[K * K + m]) * r;
+        out[((int64_t(e) * K + m) * a.s + i) * N3 + v] = F[m] + T(a.dt) * T(a.coef[K * K + m]) * r;
     }
 }
 
-template <typename T>
-hipError_t run_transport(const dgfs_slab& S, const void* in, void* out, double dt, double* nw, hipStream_t st) {
+template <typename T, int N>
+hipError_t run_transport(const dgfs_slab& S, const void* in, void* out, double dt, double* part, hipStream_t st) {
     const char* dev = static_cast<const char*>(S.dev);
-    const double* den = reinterpret_cast<const double*>(dev + S.off_den);
     const int lw = S.desc.left.kind == DGFS_BC_WALL, rw = S.desc.right.kind == DGFS_BC_WALL;
     if (lw || rw) {
-        wall_density_kernel<T><<<dim3(unsigned(2 * S.s)), dim3(256), 0, st>>>(
-            static_cast<const T*>(in), reinterpret_cast<const T*>(dev + S.off_vx), den, nw, S.s, S.N, 0,
-            S.nodes - 1, lw, rw);
+        wall_density_kernel<T, N><<<dim3(unsigned(2 * S.s * kWallBlocks)), dim3(256), 0, st>>>(
+            static_cast<const T*>(in), reinterpret_cast<const T*>(dev + S.off_vx), part, S.s, 0, S.nodes - 1, lw, rw);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -190,23 +199,34 @@ hipError_t run_transport(const dgfs_slab& S, const void* in, void* out, double d
     a.coef = reinterpret_cast<const double*>(dev + S.off_coef);
     a.vx = dev + S.off_vx;
     a.bt = dev + S.off_bt;
-    a.nw = nw;
+    a.den = reinterpret_cast<const double*>(dev + S.off_den);
+    a.part = part;
     a.Ne = S.Ne;
     a.K = S.K;
     a.s = S.s;
-    a.N = S.N;
     a.left_wall = lw;
     a.right_wall = rw;
     a.dt = dt;
-    const int64_t n = int64_t(S.Ne) * S.s * S.N * S.N * S.N;
-    transport_kernel<T><<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, st>>>(static_cast<const T*>(in),
-                                                                              static_cast<T*>(out), a);
+    const int64_t n = int64_t(S.Ne) * S.s * N * N * N;
+    transport_kernel<T, N><<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, st>>>(static_cast<const T*>(in),
+                                                                                 static_cast<T*>(out), a);
     return hipGetLastError();
 }
 
-hipError_t transport(const dgfs_slab& S, const void* in, void* out, double dt, double* nw, hipStream_t st) {
-    return S.plan->precision == DGFS_FP64 ? run_transport<double>(S, in, out, dt, nw, st)
-                                          : run_transport<float>(S, in, out, dt, nw, st);
+template <typename T>
+hipError_t transport_n(const dgfs_slab& S, const void* in, void* out, double dt, double* part, hipStream_t st) {
+    switch (S.N) {
+        case 16: return run_transport<T, 16>(S, in, out, dt, part, st);
+        case 24: return run_transport<T, 24>(S, in, out, dt, part, st);
+        case 32: return run_transport<T, 32>(S, in, out, dt, part, st);
+        case 48: return run_transport<T, 48>(S, in, out, dt, part, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t transport(const dgfs_slab& S, const void* in, void* out, double dt, double* part, hipStream_t st) {
+    return S.plan->precision == DGFS_FP64 ? transport_n<double>(S, in, out, dt, part, st)
+                                          : transport_n<float>(S, in, out, dt, part, st);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -232,6 +252,9 @@ dgfs_status check_boundary(const dgfs_boundary& b, int s) {
 }
 
 size_t state_bytes(const dgfs_slab& S) { return align256(size_t(S.nodes) * S.s * S.plan->n3() * S.plan->elem()); }
+
+// wall-density partials: [2 sides][8 species][kWallBlocks] doubles
+constexpr size_t kPartBytes = 2 * 8 * kWallBlocks * sizeof(double);
 
 }  // namespace
 
@@ -344,9 +367,9 @@ dgfs_status dgfs_slab_workspace_size(const dgfs_slab* slab, int32_t scheme, size
         dgfs_status st = dgfs_workspace_size(slab->plan, slab->nodes, &cw);
         if (st != DGFS_OK) return st;
     }
-    // f1, f2 (SSP-RK2) or f1 (Euler), Q, the wall densities, the collide workspace
+    // f1, f2 (SSP-RK2) or f1 (Euler), Q, the wall-density partials, the collide workspace
     const size_t sb = state_bytes(*slab);
-    *bytes = sb * (scheme == DGFS_SSPRK2 ? 3 : 2) + 256 + cw;
+    *bytes = sb * (scheme == DGFS_SSPRK2 ? 3 : 2) + kPartBytes + cw;
     return DGFS_OK;
 }
 
@@ -371,8 +394,8 @@ dgfs_status dgfs_slab_step(const dgfs_slab* slab, void* f, double dt, int32_t st
     void* f2 = scheme == DGFS_SSPRK2 ? w + sb : nullptr;
     void* Q = w + sb * (scheme == DGFS_SSPRK2 ? 2 : 1);
     double* nw = reinterpret_cast<double*>(w + sb * (scheme == DGFS_SSPRK2 ? 3 : 2));
-    void* cw = w + sb * (scheme == DGFS_SSPRK2 ? 3 : 2) + 256;
-    const size_t cwb = ws_bytes - (sb * (scheme == DGFS_SSPRK2 ? 3 : 2) + 256);
+    void* cw = w + sb * (scheme == DGFS_SSPRK2 ? 3 : 2) + kPartBytes;
+    const size_t cwb = ws_bytes - (sb * (scheme == DGFS_SSPRK2 ? 3 : 2) + kPartBytes);
     hipStream_t st = static_cast<hipStream_t>(stream);
     auto dev = [&](hipError_t e) {
         return e == hipSuccess ? DGFS_OK
