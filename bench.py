@@ -65,9 +65,10 @@ def gain_flops_per_node(N, M, n_rho, s, antipodal=True):
 
 
 def gain_flops_per_node_vss(N, M, n_rho, s, antipodal=True):
-    """The same for a VSS kernel, whose kernel mode depends on the direction: per class
-    (one direction), radial point: two inverse 3-D FFTs with their phase products, the
-    complex product-accumulate (12 flops per point) and one forward 3-D FFT."""
+    """The same for a VSS kernel, whose kernel mode depends on the direction: per
+    direction and radial point two inverse 3-D FFTs with their phase products, the
+    complex product (12 flops per point) and one forward 3-D FFT (the library transforms
+    the real parts of two directions together: the model counts the method's work)."""
     n3 = N ** 3
     fft = 5.0 * n3 * math.log2(n3)
     dirs = s * (M // 2) + (s * (s - 1) // 2) * M if antipodal else s * s * M
@@ -256,13 +257,14 @@ def vss_leg(torch, dev, calls):
     ms_call = e0.elapsed_time(e1) / calls
     stage /= calls
     flops = w["batch"] * gain_flops_per_node_vss(w["N"], w["M"], w["n_rho"], s)
-    # radial stage bytes: each direction's whole-spectrum partial read once per node, the
-    # two complex tables of each (direction, target) use once per group of 4 nodes, the
-    # gain and loss spectra written, the loss terms' f_hat read
+    # radial stage bytes: each class's (two directions) whole-spectrum partial read once
+    # per node, the F_H table of each (direction, target) use once per group of 4 nodes,
+    # the gain and loss spectra written, the loss terms' f_hat read (the F_A table and the
+    # Nyquist-plane spectra, read only by lanes on those planes, are not counted)
     N3, NREP = w["N"] ** 3, w["N"] * w["N"] * (w["N"] // 2 + 1)
     dirs = s * (w["M"] // 2) + (s * (s - 1) // 2) * w["M"]
     uses = s * (w["M"] // 2) + s * (s - 1) * w["M"]
-    radial_bytes = w["batch"] * (dirs * w["n_rho"] * N3 * 8 + uses * w["n_rho"] * 2 * NREP * 8 / 4
+    radial_bytes = w["batch"] * ((dirs // 2) * w["n_rho"] * N3 * 8 + uses * w["n_rho"] * NREP * 8 / 4
                                  + 2 * s * N3 * 8 + s * s * N3 * 8)
     res = {"workload": "VSS slab: 256 nodes, argon-krypton VSS kernels (omega 0.81/0.805/0.8, alpha "
                        "1.4/1.36/1.32, m2/m1 = 2.098), N=32, L=6, M=12, N_rho=16, bi-Maxwellian + 1e-2 noise, "

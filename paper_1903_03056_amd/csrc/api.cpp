@@ -200,14 +200,15 @@ std::vector<double> conserve_pack(const std::vector<double>& mass, const std::ve
 }
 
 // Build every host table and lay it out in one byte blob for the device.
-// Kernel-mode tables of one VSS class (one direction sigma) for one target species,
-// [nrho][2][N][N][N/2+1] complex over the stored half k_z <= N/2:
-//   T1(q, k) = w_rho_q w_sigma F(mode of k, rho_q, sigma_eff) / N^3,
+// Kernel-mode tables of one VSS class (up to two directions) for one target species,
+// [nrho][2 directions][2][N][N][N/2+1] complex over the stored half k_z <= N/2: with
+//   T1(q, k) = w_rho_q w_sigma F(mode of k, rho_q, sigma_eff) / N^3 and
 //   T2(q, k) = conj of the same at the mode of the mirror index (-k) mod N,
-// sigma_eff = sigma for the class's own ordering (i, j) and -sigma for the target j of an
-// unlike class (its products are those of (j, i) at -sigma).  A like class that keeps one
-// of each antipodal pair adds F(k, -sigma) = conj F(k, sigma): 2 Re F.  T2 differs from T1
-// only where k has a component at the Nyquist index, whose mirror is not the mode -k.
+// the entries are F_H = (T1 + T2)/2 and F_A = (T1 - T2)/2 (F_A vanishes unless k has a
+// component at the Nyquist index, whose mirror is not the mode -k).  sigma_eff = sigma
+// for the class's own ordering (i, j) and -sigma for the target j of an unlike class (its
+// products are those of (j, i) at -sigma).  A like class that keeps one of each antipodal
+// pair adds F(k, -sigma) = conj F(k, sigma): 2 Re F.  A missing second direction is zero.
 void vss_table(const dgfs_plan& P, const dgfs::GainClass& c, bool own, const dgfs::PairParams& pp,
                std::vector<std::complex<double>>& out) {
     const int N = P.N, KZH = N / 2 + 1, nrho = P.nrho;
@@ -216,13 +217,11 @@ void vss_table(const dgfs_plan& P, const dgfs::GainClass& c, bool own, const dgf
     const double wsig = 4.0 * kPi / P.M;
     const size_t nrep = size_t(N) * N * KZH;
     const size_t base = out.size();
-    out.resize(base + size_t(nrho) * 2 * nrep);
+    out.resize(base + size_t(nrho) * 4 * nrep, std::complex<double>(0.0, 0.0));
     auto mode = [N](int idx) { return double(idx < N / 2 ? idx : idx - N); };
-    const double* s0 = &P.sigma[3 * c.dirs[0]];
-    const double sg[3] = {own ? s0[0] : -s0[0], own ? s0[1] : -s0[1], own ? s0[2] : -s0[2]};
     const int K2 = P.K2;
     for (int q = 0; q < nrho; ++q) {
-        // j_l(z) per |k|^2, shared by every mode of this radial point
+        // j_l(z) per |k|^2, shared by every direction and mode of this radial point
         const double rho = pp.rho[q];
         const double zmax = kPi * pp.a * rho * std::sqrt(double(K2 - 1)) / L;
         const int lmax = dgfs::pre::vss_terms(zmax);
@@ -235,29 +234,35 @@ void vss_table(const dgfs_plan& P, const dgfs::GainClass& c, bool own, const dgf
             dgfs::pre::sph_bessel(nterm[k2] - 1, z, jtab[k2]);
         }
         const double pref = pp.C * std::pow(rho, pp.gamma + 2.0) * pp.wrho[q] * wsig / n3;
-        auto Feff = [&](const double k[3]) {
-            const int k2 = int(std::lround(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]));
-            const double mu = k2 > 0 ? (k[0] * sg[0] + k[1] * sg[1] + k[2] * sg[2]) / std::sqrt(double(k2)) : 0.0;
-            double re, im;
-            dgfs::pre::vss_sum(S, jtab[k2].data(), nterm[k2], mu, re, im);
-            return like_half ? std::complex<double>(2.0 * re, 0.0) : std::complex<double>(re, im);
-        };
-        std::complex<double>* t1 = &out[base + (size_t(q) * 2 + 0) * nrep];
-        std::complex<double>* t2 = &out[base + (size_t(q) * 2 + 1) * nrep];
-        for (int kx = 0; kx < N; ++kx)
-            for (int ky = 0; ky < N; ++ky)
-                for (int kz = 0; kz < KZH; ++kz) {
-                    const size_t o = (size_t(kx) * N + ky) * KZH + kz;
-                    const double k[3] = {mode(kx), mode(ky), mode(kz)};
-                    const std::complex<double> v = Feff(k);
-                    t1[o] = pref * v;
-                    if (kx == N / 2 || ky == N / 2 || kz == N / 2) {
-                        const double km[3] = {mode((N - kx) % N), mode((N - ky) % N), mode((N - kz) % N)};
-                        t2[o] = pref * std::conj(Feff(km));
-                    } else {
-                        t2[o] = t1[o];  // F(-k) = conj F(k)
+        for (int d = 0; d < c.ndir; ++d) {
+            const double* s0 = &P.sigma[3 * c.dirs[d]];
+            const double sg[3] = {own ? s0[0] : -s0[0], own ? s0[1] : -s0[1], own ? s0[2] : -s0[2]};
+            auto Feff = [&](const double k[3]) {
+                const int k2 = int(std::lround(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]));
+                const double mu =
+                    k2 > 0 ? (k[0] * sg[0] + k[1] * sg[1] + k[2] * sg[2]) / std::sqrt(double(k2)) : 0.0;
+                double re, im;
+                dgfs::pre::vss_sum(S, jtab[k2].data(), nterm[k2], mu, re, im);
+                return like_half ? std::complex<double>(2.0 * re, 0.0) : std::complex<double>(re, im);
+            };
+            std::complex<double>* th = &out[base + ((size_t(q) * 2 + d) * 2 + 0) * nrep];
+            std::complex<double>* ta = &out[base + ((size_t(q) * 2 + d) * 2 + 1) * nrep];
+            for (int kx = 0; kx < N; ++kx)
+                for (int ky = 0; ky < N; ++ky)
+                    for (int kz = 0; kz < KZH; ++kz) {
+                        const size_t o = (size_t(kx) * N + ky) * KZH + kz;
+                        const double k[3] = {mode(kx), mode(ky), mode(kz)};
+                        const std::complex<double> t1 = pref * Feff(k);
+                        if (kx == N / 2 || ky == N / 2 || kz == N / 2) {
+                            const double km[3] = {mode((N - kx) % N), mode((N - ky) % N), mode((N - kz) % N)};
+                            const std::complex<double> t2 = pref * std::conj(Feff(km));
+                            th[o] = 0.5 * (t1 + t2);
+                            ta[o] = 0.5 * (t1 - t2);
+                        } else {
+                            th[o] = t1;  // F(-k) = conj F(k): no anti-Hermitian part
+                        }
                     }
-                }
+        }
     }
 }
 
@@ -531,9 +536,9 @@ dgfs_status create_single(const dgfs_problem* problem, const std::vector<unsigne
                 P->classes.push_back(c);
                 continue;
             }
-            for (int d : dirs) {
-                c.dirs.assign(1, d);
-                c.ndir = 1;
+            for (size_t d0 = 0; d0 < dirs.size(); d0 += 2) {  // two directions per class
+                c.dirs.assign(dirs.begin() + d0, dirs.begin() + std::min(dirs.size(), d0 + 2));
+                c.ndir = int(c.dirs.size());
                 c.weight = 1.0;
                 c.dir_offset = off;
                 off += c.ndir;
@@ -730,8 +735,10 @@ size_t dgfs_plan::ws_per_node(bool pairs) const {
     }
     const size_t c = 2 * elem() * n3();
     // a partial: the Hermitian half of a real field's spectrum, or (VSS) the whole
-    // spectrum of the complex field S_0 + i S_1
-    const size_t part = vss ? 2 * elem() * n3() : 2 * elem() * size_t(N) * N * (N / 2 + 1);
+    // spectrum of Re S_0 + i Re S_1 plus the Nyquist-plane sums of Im S_d and their DFTs
+    const size_t N2 = size_t(N) * N;
+    const size_t part = vss ? 2 * elem() * n3() + elem() * 2 * (2 + size_t(geo.CH)) * N2 + 2 * elem() * 3 * N2
+                            : 2 * elem() * size_t(N) * N * (N / 2 + 1);
     const int nslots = pairs ? s * s : s;
     if (inner)
         return dgfs::dealias_ws_per_node(elem(), N, s, int(inner->classes.size()), inner->nrho, nslots);

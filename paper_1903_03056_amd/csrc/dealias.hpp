@@ -225,6 +225,7 @@ hipError_t run_dealiased(const dgfs_plan& outer, const dgfs_plan& inner, const T
     GainArgs<T> ga;
     ga.fhat = fHK;
     ga.P = P;
+    ga.PL = nullptr;
     ga.kx = reinterpret_cast<const cx<T>*>(dev + inner.off_kx);
     ga.yz = reinterpret_cast<const cx<T>*>(dev + inner.off_yz);
     ga.nyq = reinterpret_cast<const T*>(dev + inner.off_nyq);
@@ -235,7 +236,8 @@ hipError_t run_dealiased(const dgfs_plan& outer, const dgfs_plan& inner, const T
     ga.nrho = inner.nrho;
     ga.nb = nb;
     const int64_t groups = ((nb + 7) / 8) * 8 * int64_t(4 * ncls) * inner.nrho * CH;
-    gain_kernel<T, NI, CH, CZ, PIPE, false, true><<<dim3(unsigned(groups)), dim3(GainK<T, NI, CH, CZ>::NT), 0, st>>>(ga);
+    gain_kernel<T, NI, CH, CZ, PIPE, false, GAIN_COMPLEX>
+        <<<dim3(unsigned(groups)), dim3(GainK<T, NI, CH, CZ>::NT), 0, st>>>(ga);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     mark(2);
 

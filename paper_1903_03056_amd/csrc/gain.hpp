@@ -15,6 +15,18 @@
 namespace dgfs {
 
 // ================================================================ gain kernel
+// What a gain work item accumulates and stores:
+// GAIN_REAL     Re S summed over the class's directions (VHS: F real and even in k);
+//               the Hermitian half of the partial is stored.
+// GAIN_COMPLEX  the complex S summed over the class's directions, whole spectrum stored
+//               (the dealiased form, whose inputs are not spectra of real fields).
+// GAIN_VSS      VSS (F depends on sigma): a class holds at most two directions; their
+//               real parts are transformed together as Re S_0 + i Re S_1 (whole spectrum
+//               stored), and their imaginary parts, which reach the result only on the
+//               planes k_x, k_y or k_z = N/2 (the literal Nyquist reading), are reduced
+//               to those planes (sums with (-1)^x, (-1)^y, (-1)^z) and stored.
+enum { GAIN_REAL = 0, GAIN_COMPLEX = 1, GAIN_VSS = 2 };
+
 // Geometry of one work item: the x-chunk c (x-indices = c mod CH, NP = N/CH of them)
 // of one S_q field.  Each y/z pencil of the chunk is shared by CZ thread groups: group
 // cz keeps the outputs with index = cz mod CZ (decimation in frequency), so a thread
@@ -46,7 +58,9 @@ template <typename T>
 struct GainArgs {
     const cx<T>* fhat;  // [nb][s][N^3], DFT / N^3
     cx<T>* P;           // [nb][ncls][nrho][CH][N/CH][N][N/2+1]  (k_z <= N/2 of each partial);
-                        // VSS: [nb][ncls][nrho][CH][N/CH][N][N]  (the whole spectrum)
+                        // GAIN_COMPLEX, GAIN_VSS: [nb][ncls][nrho][CH][N/CH][N][N]  (whole spectrum)
+    T* PL;              // GAIN_VSS: [nb][ncls][nrho][2][(2 + CH) N^2]  Nyquist-plane sums of Im S_d:
+                        //   [x][y] over z, [x][z] over y, then per chunk [y][z] over its x
     const cx<T>* kx;    // [dirs][nrho][2][CH][N]  x-phase merged with the chunk split
     const cx<T>* yz;    // [dirs][nrho][2][2][N]   y- and z-phases
     const T* nyq;       // [dirs][nrho][2]         2 sin(theta_x N / 2) of the x-phase
@@ -550,10 +564,11 @@ __device__ __forceinline__ void packed_direction(const cx<T>* __restrict__ fa, c
     __syncthreads();
 }
 
-template <typename T, int N, int CH, int CZ, bool PIPE, bool PACK, bool VSS>
+template <typename T, int N, int CH, int CZ, bool PIPE, bool PACK, int MODE>
 __global__ __launch_bounds__((GainK<T, N, CH, CZ>::NT)) void gain_kernel(GainArgs<T> a) {
     using K = GainK<T, N, CH, CZ>;
-    static_assert(!(PACK && VSS), "the packed two-field form keeps only Re(A B)");
+    constexpr bool CPLX = MODE != GAIN_REAL;  // the whole spectrum of a complex field is stored
+    static_assert(!(PACK && CPLX), "the packed two-field form keeps only Re(A B)");
     __shared__ cx<T> buf[K::LDS + ((PACK && pack_ok<T, N, CH, CZ>()) ? K::LINES : 0)];
     // Work items of one node are placed on one XCD (workgroups are dealt to the 8
     // XCDs round-robin), so that node's spectra stay in that XCD's L2.
@@ -580,14 +595,43 @@ __global__ __launch_bounds__((GainK<T, N, CH, CZ>::NT)) void gain_kernel(GainArg
     // VHS: only Re(S_q) reaches the result, since the radial operator multiplies
     // DFT(S_q) by a real F that is even in k: Re IDFT(F DFT(S)) = IDFT(F DFT(Re S)).
     // VSS: F depends on the direction and, at indices with a Nyquist component, F at the
-    // mode of k is not the conjugate of F at the mode of the mirror index, so the
-    // imaginary part of S (from the Nyquist modes of the shifted fields) contributes:
-    // the class's one direction keeps S = S + i S1 whole.
-    T S[K::NS], S1[VSS ? K::NS : 1];
+    // mode of k is not the conjugate of F at the mode of the mirror index, so there the
+    // imaginary part of S (from the Nyquist modes of the shifted fields) contributes.
+    T S[K::NS], S1[CPLX ? K::NS : 1];
 #pragma unroll
     for (int n = 0; n < K::NS; ++n) S[n] = T(0);
 #pragma unroll
-    for (int n = 0; n < (VSS ? K::NS : 1); ++n) S1[n] = T(0);
+    for (int n = 0; n < (CPLX ? K::NS : 1); ++n) S1[n] = T(0);
+
+    // GAIN_VSS: reduce Im S of direction d (in im[]) to the three Nyquist planes
+    auto nyquist_planes = [&](int d, const T* im) {
+        constexpr int N2 = N * N;
+        T* PL = a.PL + (((int64_t(b) * a.ncls + cl) * a.nrho + q) * 2 + d) * int64_t((2 + CH) * N2);
+#pragma unroll
+        for (int j = 0; j < K::NS; ++j) buf[(m * N + r) * K::ROW + CZ * j + cz] = cx<T>{im[j], T(0)};
+        __syncthreads();
+        if (cz == 0) {  // over z: [x][y]
+            T acc = T(0);
+            for (int z = 0; z < N; ++z) acc += (z & 1) ? -buf[(m * N + r) * K::ROW + z].x : buf[(m * N + r) * K::ROW + z].x;
+            PL[(c + CH * m) * N + r] = acc;
+        }
+        for (int e = tid; e < K::NP * N; e += K::NT) {  // over y: [x][z]
+            const int mm = e / N, z = e % N;
+            T acc = T(0);
+            for (int y = 0; y < N; ++y) acc += (y & 1) ? -buf[(mm * N + y) * K::ROW + z].x : buf[(mm * N + y) * K::ROW + z].x;
+            PL[N2 + (c + CH * mm) * N + z] = acc;
+        }
+        for (int e = tid; e < N2; e += K::NT) {  // over this chunk's x: [y][z]
+            const int y = e / N, z = e % N;
+            T acc = T(0);
+            for (int mm = 0; mm < K::NP; ++mm) {
+                const T v = buf[(mm * N + y) * K::ROW + z].x;
+                acc += ((c + CH * mm) & 1) ? -v : v;
+            }
+            PL[2 * N2 + c * N2 + e] = acc;
+        }
+        __syncthreads();
+    };
 
     auto direction = [&](int d, T* Sd) {
         const int64_t base = (int64_t(doff + d) * a.nrho + q) * 2;
@@ -603,18 +647,37 @@ __global__ __launch_bounds__((GainK<T, N, CH, CZ>::NT)) void gain_kernel(GainArg
                                            a.nyq[base + 1], c, buf, cz, m, r, B);
 #pragma unroll
             for (int n = 0; n < K::NS; ++n) Sd[n] = fma(w, fma(A[n].x, B[n].x, -A[n].y * B[n].y), Sd[n]);
-            if constexpr (VSS) {
+            if constexpr (MODE == GAIN_COMPLEX) {
 #pragma unroll
                 for (int n = 0; n < K::NS; ++n) S1[n] = fma(w, fma(A[n].x, B[n].y, A[n].y * B[n].x), S1[n]);
             }
+            if constexpr (MODE == GAIN_VSS) {
+                T im[K::NS];
+#pragma unroll
+                for (int n = 0; n < K::NS; ++n) im[n] = w * fma(A[n].x, B[n].y, A[n].y * B[n].x);
+                nyquist_planes(d, im);
+            }
         }
     };
-    for (int d = 0; d < ndir; ++d) direction(d, S);
+    if constexpr (MODE == GAIN_VSS) {
+        direction(0, S);
+        if (ndir > 1) {
+            direction(1, S1);
+        } else {  // a one-direction class: its second plane sums are zero
+            T zero[K::NS];
+#pragma unroll
+            for (int n = 0; n < K::NS; ++n) zero[n] = T(0);
+            nyquist_planes(1, zero);
+        }
+    } else {
+        for (int d = 0; d < ndir; ++d) direction(d, S);
+    }
 
-    // forward DFT of Re S_q (VSS: of S + i S1): z and y through LDS, then the chunk's part of x
+    // forward DFT of Re S_q (complex modes: of S + i S1): z and y through LDS, then the
+    // chunk's part of x
 #pragma unroll
     for (int j = 0; j < K::NS; ++j) {
-        if constexpr (VSS) buf[(m * N + r) * K::ROW + CZ * j + cz] = cx<T>{S[j], S1[j]};
+        if constexpr (CPLX) buf[(m * N + r) * K::ROW + CZ * j + cz] = cx<T>{S[j], S1[j]};
         else buf[(m * N + r) * K::ROW + CZ * j + cz] = cx<T>{S[j], T(0)};
     }
     __syncthreads();
@@ -635,7 +698,7 @@ __global__ __launch_bounds__((GainK<T, N, CH, CZ>::NT)) void gain_kernel(GainArg
         for (int j = 0; j < K::NS; ++j) buf[(m * N + CZ * j + cz) * K::ROW + r] = v[j];
         __syncthreads();
     }
-    if constexpr (VSS) {
+    if constexpr (CPLX) {
         // the transform of a complex field: every (k_y, k_z) pencil is stored
         constexpr int64_t PCHF = int64_t(K::NP) * K::NPENF;
         cx<T>* Pout = a.P + ((int64_t(b) * a.ncls + cl) * a.nrho + q) * (CH * PCHF) + int64_t(c) * PCHF;
@@ -673,6 +736,89 @@ __global__ __launch_bounds__((GainK<T, N, CH, CZ>::NT)) void gain_kernel(GainArg
 }
 
 // =============================================================== radial kernel
+// VSS: the Hermitian part of sum_d F_d DFT(S_d), with S_d = Re S_d + i Im S_d, Z the
+// spectrum of Re S_0 + i Re S_1 and V_d = DFT(Im S_d):
+//   sum_d F_H,d U_d + i F_A,d V_d,  U_0 = (Z(k) + conj Z(-k))/2, U_1 = (Z(k) - conj Z(-k))/(2i),
+// F_H, F_A the Hermitian and anti-Hermitian parts of F (F_A vanishes off the Nyquist
+// planes, where V_d is needed).
+template <typename T>
+__device__ __forceinline__ void vss_accumulate(cx<double>& acc, const cx<T> h[2], const cx<T> fa[2], double u0x,
+                                               double u0y, double u1x, double u1y, bool nyq, const cx<T> v[2]) {
+    acc.x += double(h[0].x) * u0x - double(h[0].y) * u0y + double(h[1].x) * u1x - double(h[1].y) * u1y;
+    acc.y += double(h[0].x) * u0y + double(h[0].y) * u0x + double(h[1].x) * u1y + double(h[1].y) * u1x;
+    if (nyq) {
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {  // i F_A V
+            acc.x -= double(fa[d].x) * double(v[d].y) + double(fa[d].y) * double(v[d].x);
+            acc.y += double(fa[d].x) * double(v[d].x) - double(fa[d].y) * double(v[d].y);
+        }
+    }
+}
+
+// Plane and index of mode k in the V array (k has a component at the Nyquist index).
+template <int N>
+__device__ __forceinline__ int vplane_index(int kx, int ky, int kz) {
+    if (kz == N / 2) return 0 * N * N + kx * N + ky;
+    if (ky == N / 2) return 1 * N * N + kx * N + kz;
+    return 2 * N * N + ky * N + kz;
+}
+
+// W = DFT(Im S_0 + i Im S_1) on the three Nyquist planes from the plane sums: one block
+// per (node, class, rho), one thread group of N per plane; the first pass transforms
+// along the plane's first axis (coalesced column reads), the second along its second
+// axis, the result leaves through LDS with coalesced stores.  Each V_d = DFT(Im S_d) is
+// Hermitian on its plane, so the radial kernel separates them from W at k and at the
+// plane mirror of k.
+template <typename T, int N, int CH>
+__global__ __launch_bounds__(3 * N) void nyquist_dft_kernel(const T* __restrict__ PL, cx<T>* __restrict__ V) {
+    constexpr int N2 = N * N;
+    const int64_t it = blockIdx.x;  // (node, class, rho)
+    const int plane = threadIdx.x / N, t = threadIdx.x % N;
+    __shared__ cx<T> Ls[3][N][N + 1];
+    const T* p0 = PL + (it * 2 + 0) * int64_t((2 + CH) * N2);
+    const T* p1 = PL + (it * 2 + 1) * int64_t((2 + CH) * N2);
+    auto at = [&](const T* pl, int r) {
+        if (plane < 2) return pl[plane * N2 + r * N + t];
+        T v = T(0);
+#pragma unroll
+        for (int c = 0; c < CH; ++c) v += pl[2 * N2 + c * N2 + r * N + t];
+        return v;
+    };
+    {
+        cx<T> x[N];  // column t of the plane, transformed along its first axis
+#pragma unroll
+        for (int r = 0; r < N; ++r) x[r] = cx<T>{at(p0, r), at(p1, r)};
+        fft<N, -1>(x);
+#pragma unroll
+        for (int k = 0; k < N; ++k) Ls[plane][k][t] = x[k];
+    }
+    __syncthreads();
+    {
+        cx<T> x[N];  // row t (first-axis mode t), transformed along the second axis
+#pragma unroll
+        for (int c2 = 0; c2 < N; ++c2) x[c2] = Ls[plane][t][c2];
+        fft<N, -1>(x);
+#pragma unroll
+        for (int k = 0; k < N; ++k) Ls[plane][t][k] = x[k];
+    }
+    __syncthreads();
+    cx<T>* out = V + it * int64_t(3 * N2) + plane * N2;
+    for (int row = 0; row < N; ++row) out[row * N + t] = Ls[plane][row][t];
+}
+
+// The plane-mirror of mode index k in the W array (same plane, other two indices negated).
+template <int N>
+__device__ __forceinline__ int vplane_mirror(int kx, int ky, int kz) {
+    return vplane_index<N>((N - kx) % N, (N - ky) % N, kz == N / 2 ? kz : (N - kz) % N);
+}
+
+// V_0 and V_1 at k from W at k and at its plane mirror.
+template <typename T>
+__device__ __forceinline__ void split_w(const cx<T>& W, const cx<T>& Wm, cx<T> v[2]) {
+    v[0] = cx<T>{T(0.5) * (W.x + Wm.x), T(0.5) * (W.y - Wm.y)};
+    v[1] = cx<T>{T(0.5) * (W.y + Wm.y), T(0.5) * (Wm.x - W.x)};
+}
+
 template <typename T>
 struct RadialArgs {
     const cx<T>* P;
@@ -680,8 +826,9 @@ struct RadialArgs {
     cx<T>* Gt;          // [nb][nslots][N^3]
     cx<T>* Lt;          // [nb][nslots][N^3]
     const T* F;         // [nftab][nrho][K2]  w_q F(|k|, rho_q) / N^3
-    const cx<T>* Fv;    // VSS: [nftab][nrho][2][N][N][N/2+1]  T1, T2 (w_q w_sigma F / N^3 at k, and the
-                        //      conjugate at the mirror index)
+    const cx<T>* Fv;    // VSS: [nftab][nrho][2 directions][2][N][N][N/2+1]  F_H, F_A: the Hermitian and
+                        //      anti-Hermitian parts (in the index sense) of w_q w_sigma F / N^3
+    const cx<T>* V;     // VSS: [nb][ncls][nrho][3][N^2]  DFT(Im S_0 + i Im S_1) on the planes k_z, k_y, k_x = N/2
     const T* G;         // [ngtab][K2]        G-(|k|)
     const cx<T>* tw;    // [N][CH]  e^{-2 pi i kx c / N}
     const int* slots;   // [nslots][5]
@@ -697,10 +844,9 @@ struct RadialArgs {
 // L(k) = sum_j G-(|k|) f_hat^j(k) for the CH x-modes k_x = k_xp + j N/CH, and writes
 // both at k and their conjugates at -k (S_q and f are real, F and G- are real and even
 // in k).  Pairs with k_z = 0 or N/2 lie wholly in the stored half and are written once.
-// VSS: each class (one direction) partial is the whole spectrum Z of the complex S; the
-// Hermitian part of F(mode of k) Z(k), the part that reaches the real result, is
-// (T1(k) Z(k) + T2(k) conj Z(-k)) / 2 with T1 = F at the mode of k and T2 = conj F at the
-// mode of the mirror index (-k) mod N; the thread reads Z at k and -k.
+// VSS: each class (up to two directions) partial is the whole spectrum Z of
+// Re S_0 + i Re S_1; the thread reads Z at k and -k and adds the Nyquist-plane terms
+// (vss_accumulate).
 template <typename T, int N, int CH, bool VSS>
 __global__ __launch_bounds__(256) void radial_kernel(RadialArgs<T> a) {
     constexpr int NP = N / CH;
@@ -736,7 +882,8 @@ __global__ __launch_bounds__(256) void radial_kernel(RadialArgs<T> a) {
         for (int gi = 0; gi < ng; ++gi) {
             const int cl = a.gterms[2 * (g0 + gi)], ft = a.gterms[2 * (g0 + gi) + 1];
             const cx<T>* Pb = a.P + (int64_t(b) * a.ncls + cl) * a.nrho * (CH * PCHF);
-            const cx<T>* Fb = a.Fv + int64_t(ft) * a.nrho * 2 * NREP + (int64_t(kxp) * N + ky) * KZH + kz;
+            const cx<T>* Fb = a.Fv + int64_t(ft) * a.nrho * 4 * NREP + (int64_t(kxp) * N + ky) * KZH + kz;
+            const cx<T>* Vb = a.V + (int64_t(b) * a.ncls + cl) * a.nrho * (3 * N2);
             for (int q = 0; q < a.nrho; ++q) {
                 cx<T> pc[CH], pm[CH];
 #pragma unroll
@@ -753,13 +900,19 @@ __global__ __launch_bounds__(256) void radial_kernel(RadialArgs<T> a) {
                         cmac(Z, a.tw[kx * CH + c], pc[c]);
                         cmac(Zm, a.tw[kxm * CH + c], pm[c]);
                     }
-                    const cx<T> t1 = Fb[(int64_t(q) * 2 + 0) * NREP + int64_t(j) * NP * N * KZH];
-                    const cx<T> t2 = Fb[(int64_t(q) * 2 + 1) * NREP + int64_t(j) * NP * N * KZH];
-                    // t1 Z + t2 conj(Zm), halved
-                    acc[j].x += 0.5 * (double(t1.x) * Z.x - double(t1.y) * Z.y + double(t2.x) * Zm.x +
-                                       double(t2.y) * Zm.y);
-                    acc[j].y += 0.5 * (double(t1.x) * Z.y + double(t1.y) * Z.x - double(t2.x) * Zm.y +
-                                       double(t2.y) * Zm.x);
+                    cx<T> h[2], fa[2], v[2];
+#pragma unroll
+                    for (int d = 0; d < 2; ++d) {
+                        h[d] = Fb[((int64_t(q) * 2 + d) * 2 + 0) * NREP + int64_t(j) * NP * N * KZH];
+                        fa[d] = Fb[((int64_t(q) * 2 + d) * 2 + 1) * NREP + int64_t(j) * NP * N * KZH];
+                    }
+                    const bool nyq = kx == N / 2 || ky == N / 2 || kz == N / 2;
+                    if (nyq)
+                        split_w<T>(Vb[int64_t(q) * (3 * N2) + vplane_index<N>(kx, ky, kz)],
+                                   Vb[int64_t(q) * (3 * N2) + vplane_mirror<N>(kx, ky, kz)], v);
+                    vss_accumulate<T>(acc[j], h, fa, 0.5 * (double(Z.x) + double(Zm.x)),
+                                      0.5 * (double(Z.y) - double(Zm.y)), 0.5 * (double(Z.y) + double(Zm.y)),
+                                      0.5 * (double(Zm.x) - double(Z.x)), nyq, v);
                 }
             }
         }
@@ -816,9 +969,10 @@ __global__ __launch_bounds__(256) void radial_kernel(RadialArgs<T> a) {
     }
 }
 
-// VSS radial sum with every slot of NB nodes in one thread: per class (one direction)
-// and radial point the two table values of each of its (at most two) uses are loaded
-// once and applied to the NB nodes' partials, which are each read once.  The per-slot
+// VSS radial sum with every slot of NB nodes in one thread: per class (up to two
+// directions), use and radial point the table values are loaded once and applied to the
+// NB nodes' partials (read at k and -k; the second use of an unlike class finds them in
+// L2).  The per-slot
 // accumulators are indexed with compile-time slots (SMAX >= nslots) under uniform
 // compares, so they stay in registers.  Loss terms and outputs as in radial_kernel.
 template <typename T, int N, int CH, int NB, int SMAX>
@@ -845,26 +999,48 @@ __global__ __launch_bounds__(256) void radial_vss_kernel(RadialArgs<T> a) {
 #pragma unroll
             for (int j = 0; j < CH; ++j) acc[u][sl][j] = cx<double>{0.0, 0.0};
 
+    constexpr int N2I = N * N;
+    bool nyq[CH];
+    bool nyq_any = false;
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+        nyq[j] = kxp + j * NP == N / 2 || ky == N / 2 || kz == N / 2;
+        nyq_any = nyq_any || nyq[j];
+    }
     for (int cl = 0; cl < a.ncls; ++cl) {
         const int s0 = a.cuses[4 * cl], s1 = a.cuses[4 * cl + 2];
         if (s0 < 0) continue;
-        const cx<T>* F0 = a.Fv + int64_t(a.cuses[4 * cl + 1]) * a.nrho * 2 * NREP + fo;
-        const cx<T>* F1 = a.Fv + int64_t(s1 >= 0 ? a.cuses[4 * cl + 3] : a.cuses[4 * cl + 1]) * a.nrho * 2 * NREP + fo;
+        const cx<T>* F0 = a.Fv + int64_t(a.cuses[4 * cl + 1]) * a.nrho * 4 * NREP + fo;
+        const cx<T>* F1 = a.Fv + int64_t(s1 >= 0 ? a.cuses[4 * cl + 3] : a.cuses[4 * cl + 1]) * a.nrho * 4 * NREP + fo;
         for (int q = 0; q < a.nrho; ++q) {
-            cx<T> t10[CH], t20[CH], t11[CH], t21[CH];
+            // F_H of both uses and both directions; F_A only where some lane has a Nyquist mode
+            cx<T> h0[CH][2], h1[CH][2], a0[CH][2], a1[CH][2];
 #pragma unroll
-            for (int j = 0; j < CH; ++j) {
-                const int64_t o = int64_t(j) * NP * N * KZH;
-                t10[j] = F0[(int64_t(q) * 2 + 0) * NREP + o];
-                t20[j] = F0[(int64_t(q) * 2 + 1) * NREP + o];
-                t11[j] = F1[(int64_t(q) * 2 + 0) * NREP + o];
-                t21[j] = F1[(int64_t(q) * 2 + 1) * NREP + o];
+            for (int j = 0; j < CH; ++j)
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    const int64_t o = ((int64_t(q) * 2 + d) * 2) * NREP + int64_t(j) * NP * N * KZH;
+                    h0[j][d] = F0[o];
+                    h1[j][d] = F1[o];
+                    a0[j][d] = cx<T>{T(0), T(0)};
+                    a1[j][d] = cx<T>{T(0), T(0)};
+                }
+            if (nyq_any) {
+#pragma unroll
+                for (int j = 0; j < CH; ++j)
+#pragma unroll
+                    for (int d = 0; d < 2; ++d) {
+                        const int64_t o = ((int64_t(q) * 2 + d) * 2 + 1) * NREP + int64_t(j) * NP * N * KZH;
+                        a0[j][d] = F0[o];
+                        a1[j][d] = F1[o];
+                    }
             }
 #pragma unroll
             for (int u = 0; u < NB; ++u) {
                 const int b = b0 + u;
                 if (b >= a.nb) break;
                 const cx<T>* Pb = a.P + ((int64_t(b) * a.ncls + cl) * a.nrho + q) * (CH * PCHF);
+                const cx<T>* Vb = a.V + ((int64_t(b) * a.ncls + cl) * a.nrho + q) * (3 * N2I);
                 cx<T> pc[CH], pm[CH];
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
@@ -880,22 +1056,14 @@ __global__ __launch_bounds__(256) void radial_vss_kernel(RadialArgs<T> a) {
                         cmac(Z, a.tw[kx * CH + c], pc[c]);
                         cmac(Zm, a.tw[kxm * CH + c], pm[c]);
                     }
-                    // (t1 Z + t2 conj Zm) / 2 for each use of the class
-                    const double zx = Z.x, zy = Z.y, mx = Zm.x, my = Zm.y;
+                    cx<T> v[2];
+                    if (nyq[j]) split_w<T>(Vb[vplane_index<N>(kx, ky, kz)], Vb[vplane_mirror<N>(kx, ky, kz)], v);
+                    const double u0x = 0.5 * (double(Z.x) + double(Zm.x)), u0y = 0.5 * (double(Z.y) - double(Zm.y));
+                    const double u1x = 0.5 * (double(Z.y) + double(Zm.y)), u1y = 0.5 * (double(Zm.x) - double(Z.x));
 #pragma unroll
                     for (int sl = 0; sl < SMAX; ++sl) {
-                        if (sl == s0) {
-                            acc[u][sl][j].x += 0.5 * (double(t10[j].x) * zx - double(t10[j].y) * zy +
-                                                      double(t20[j].x) * mx + double(t20[j].y) * my);
-                            acc[u][sl][j].y += 0.5 * (double(t10[j].x) * zy + double(t10[j].y) * zx -
-                                                      double(t20[j].x) * my + double(t20[j].y) * mx);
-                        }
-                        if (sl == s1) {
-                            acc[u][sl][j].x += 0.5 * (double(t11[j].x) * zx - double(t11[j].y) * zy +
-                                                      double(t21[j].x) * mx + double(t21[j].y) * my);
-                            acc[u][sl][j].y += 0.5 * (double(t11[j].x) * zy + double(t11[j].y) * zx -
-                                                      double(t21[j].x) * my + double(t21[j].y) * mx);
-                        }
+                        if (sl == s0) vss_accumulate<T>(acc[u][sl][j], h0[j], a0[j], u0x, u0y, u1x, u1y, nyq[j], v);
+                        if (sl == s1) vss_accumulate<T>(acc[u][sl][j], h1[j], a1[j], u0x, u0y, u1x, u1y, nyq[j], v);
                     }
                 }
             }
@@ -977,6 +1145,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 template <typename T, int N, int CH, int CZ, bool PIPE, bool PACK, bool VSS>
 hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, bool pairs, hipStream_t st,
                      hipEvent_t* ev) {
+    constexpr int MODE = VSS ? GAIN_VSS : GAIN_REAL;
     auto mark = [&](int k) {
         if (ev) hipEventRecord(ev[k], st);
     };
@@ -988,6 +1157,14 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
     w += align256(sizeof(cx<T>) * nb * p.s * N3);
     cx<T>* P = reinterpret_cast<cx<T>*>(w);
     w += align256(sizeof(cx<T>) * int64_t(nb) * ncls * p.nrho * (VSS ? N3 : (N3 / N) * (N / 2 + 1)));
+    T* PL = nullptr;
+    cx<T>* Vn = nullptr;
+    if constexpr (VSS) {
+        PL = reinterpret_cast<T*>(w);
+        w += align256(sizeof(T) * int64_t(nb) * ncls * p.nrho * 2 * (2 + CH) * N * N);
+        Vn = reinterpret_cast<cx<T>*>(w);
+        w += align256(sizeof(cx<T>) * int64_t(nb) * ncls * p.nrho * 3 * N * N);
+    }
     cx<T>* Gt = reinterpret_cast<cx<T>*>(w);
     cx<T>* Lt = Gt + int64_t(nb) * ss.nslots * N3;  // contiguous with Gt
 
@@ -1000,6 +1177,7 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
     GainArgs<T> ga;
     ga.fhat = fhat;
     ga.P = P;
+    ga.PL = PL;
     ga.kx = reinterpret_cast<const cx<T>*>(dev + p.off_kx);
     ga.yz = reinterpret_cast<const cx<T>*>(dev + p.off_yz);
     ga.nyq = reinterpret_cast<const T*>(dev + p.off_nyq);
@@ -1011,8 +1189,12 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
     ga.nb = nb;
     const int64_t ipn = int64_t(ncls) * p.nrho * CH;
     const int64_t groups = ((nb + 7) / 8) * 8 * ipn;
-    gain_kernel<T, N, CH, CZ, PIPE, PACK, VSS><<<dim3(unsigned(groups)), dim3(GainK<T, N, CH, CZ>::NT), 0, st>>>(ga);
+    gain_kernel<T, N, CH, CZ, PIPE, PACK, MODE><<<dim3(unsigned(groups)), dim3(GainK<T, N, CH, CZ>::NT), 0, st>>>(ga);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if constexpr (VSS) {
+        nyquist_dft_kernel<T, N, CH><<<dim3(unsigned(int64_t(nb) * ncls * p.nrho)), dim3(3 * N), 0, st>>>(PL, Vn);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     mark(2);
 
     RadialArgs<T> ra;
@@ -1022,6 +1204,7 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
     ra.Lt = Lt;
     ra.F = reinterpret_cast<const T*>(dev + p.off_F);
     ra.Fv = reinterpret_cast<const cx<T>*>(dev + p.off_F);
+    ra.V = Vn;
     ra.G = reinterpret_cast<const T*>(dev + p.off_G);
     ra.tw = reinterpret_cast<const cx<T>*>(dev + p.off_tw);
     ra.slots = reinterpret_cast<const int*>(dev + ss.off_slots);
