@@ -173,3 +173,27 @@ def test_vss_plain_path_is_rejected():
     plan = _plan(16, 6.0, 6, 4, "f64", _kernel())
     with pytest.raises(DgfsError):
         plan.collide_plain(torch.zeros((1, 2, 16, 16, 16), dtype=torch.float64, device="cuda"))
+
+
+def test_vss_three_species_pairs_fp64():
+    """Three species (m = 1, 2.098, 4) with VSS kernels, N = 16, M = 12, N_rho = 6, FP64:
+    the summed operator (three slots) and the pair-resolved one (nine slots, the radial
+    kernel's one-slot-per-thread form) within 1e-12 of the oracle."""
+    _require_gpu()
+    print("[case] vss three species pairs fp64", flush=True)
+    masses = (1.0, 139.1 / 66.3, 4.0)
+    om = ((0.81, 0.805, 0.79), (0.805, 0.8, 0.78), (0.79, 0.78, 0.77))
+    al = ((1.4, 1.36, 1.3), (1.36, 1.32, 1.25), (1.3, 1.25, 1.2))
+    kern = _kernel(masses, om, al)
+    N, L, M, nrho = 16, 6.0, 12, 6
+    plan = _plan(N, L, M, nrho, "f64", kern, masses=masses)
+    f = I.draw_bimaxwellian_batch(np.random.default_rng(77), 2, 3, N, (L,) * 3, masses)
+    ft = torch.tensor(f, dtype=torch.float64, device="cuda")
+    Q = plan.collide(ft).cpu().numpy()
+    Qp = plan.collide(ft, pairs=True).cpu().numpy()
+    prob = OS.Problem(masses=masses, L=L, N=N, M=M, nrho=nrho, kernel=kern)
+    for b in range(2):
+        refp = OS.collide_pairs(f[b], prob)
+        rs, rp = _rel(Q[b], refp.sum(axis=1)), _rel(Qp[b], refp)
+        print(f"node {b}: summed {rs:.3e}, pairs {rp:.3e}", flush=True)
+        assert rs <= 1e-12 and rp <= 1e-12
