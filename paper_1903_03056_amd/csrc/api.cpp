@@ -810,19 +810,17 @@ dgfs_status dgfs_plan_create(const dgfs_problem* problem, dgfs_plan** out) {
         dgfs_plan_destroy(outer);
         return st;
     }
-    // sub-classes over the split fields H_i (index i) and K_i (index s + i) of the padded
-    // spectrum P = H + i K: HH (weight w), KK (weight -w), HK and KH (weight w, their
-    // partials multiplied by i when combined)
+    // sub-classes over the fields H_i (index i), K_i (index s + i) and H_i + K_i (index
+    // 2s + i) of the padded spectrum P = H + i K: HH, KK and (H+K)(H+K), whose partials
+    // combine as Z_HH - Z_KK + i (Z_(H+K)(H+K) - Z_HH - Z_KK)
     const dgfs_plan& in = *outer->inner;
     const int nc = int(in.classes.size()), s = in.s;
     std::vector<int> cls4;
     std::vector<double> w4;
-    for (int v = 0; v < 4; ++v)
+    for (int v = 0; v < 3; ++v)
         for (const auto& c : in.classes) {
-            const int fi = (v == 1 || v == 3) ? s + c.i : c.i;
-            const int fj = (v == 1 || v == 2) ? s + c.j : c.j;
-            cls4.insert(cls4.end(), {fi, fj, c.ndir, c.dir_offset});
-            w4.push_back(v == 1 ? -c.weight : c.weight);
+            cls4.insert(cls4.end(), {v * s + c.i, v * s + c.j, c.ndir, c.dir_offset});
+            w4.push_back(c.weight);
         }
     std::vector<char> blob;
     push_int(blob, outer->off_cls4, cls4);

@@ -1,7 +1,7 @@
 // The dealiased (linear-convolution) form of eq. (sum): l + m = k with l, m, k all in
 // [-N/2, N/2-1]^3, no wrap-around.  The spectra are zero-padded to NI = 3N/2 (l + m then
 // never wraps onto a kept mode), the gain runs on the NI grid with the whole complex
-// product kept (over the two Hermitian parts of each padded spectrum), the loss product
+// product kept (over the Hermitian parts of each padded spectrum), the loss product
 // f nu is taken on the NI grid, and the kept modes are synthesised on the N grid, whose
 // real part is the result.  Included by the vss_<NI>
 // tile files, whose gain kernels keep the complex product.
@@ -35,7 +35,8 @@ __global__ __launch_bounds__(256) void pad_kernel(const cx<T>* __restrict__ fN, 
 // The padded spectrum P of a real field is not Hermitian on the NI grid (its modes with
 // a component -N/2 have no +N/2 partner), but the gain kernel's paired transforms assume
 // it.  Split exactly: P = H + i K with H(k) = (P(k) + conj P(-k))/2 and
-// K(k) = (P(k) - conj P(-k))/(2i), both Hermitian; out[b][i] = H_i, out[b][s + i] = K_i.
+// K(k) = (P(k) - conj P(-k))/(2i), both Hermitian; out[b][i] = H_i, out[b][s + i] = K_i,
+// out[b][2s + i] = H_i + K_i.
 template <typename T, int NI>
 __global__ __launch_bounds__(256) void split_kernel(const cx<T>* __restrict__ P, cx<T>* __restrict__ out, int s,
                                                     int64_t nfields) {
@@ -48,8 +49,10 @@ __global__ __launch_bounds__(256) void split_kernel(const cx<T>* __restrict__ P,
     const int em = (((NI - kx) % NI) * NI + (NI - ky) % NI) * NI + (NI - kz) % NI;
     const cx<T> p = P[t], pm = P[fld * NI3 + em];
     const int64_t b = fld / s, i = fld % s;
-    out[(b * 2 * s + i) * NI3 + e] = cx<T>{T(0.5) * (p.x + pm.x), T(0.5) * (p.y - pm.y)};
-    out[(b * 2 * s + s + i) * NI3 + e] = cx<T>{T(0.5) * (p.y + pm.y), T(0.5) * (pm.x - p.x)};
+    const cx<T> h{T(0.5) * (p.x + pm.x), T(0.5) * (p.y - pm.y)}, k{T(0.5) * (p.y + pm.y), T(0.5) * (pm.x - p.x)};
+    out[(b * 3 * s + i) * NI3 + e] = h;
+    out[(b * 3 * s + s + i) * NI3 + e] = k;
+    out[(b * 3 * s + 2 * s + i) * NI3 + e] = cx<T>{h.x + k.x, h.y + k.y};
 }
 
 struct DealiasArgs {
@@ -67,9 +70,10 @@ struct DealiasArgs {
 };
 
 // Kept gain modes: one thread per (node, slot, N-grid mode k): the chunk partials at the
-// NI index of k are combined, the four sub-classes of each class joined as
-// Z_HH - Z_KK + i (Z_HK + Z_KH) (the sign of KK is in its weight), and weighted with
-// w_q F(|k|, rho_q) / NI^3, summed over radial points and classes in FP64.
+// NI index of k are combined, the three sub-classes of each class joined as
+// Z_HH - Z_KK + i (Z_(H+K)(H+K) - Z_HH - Z_KK) (= the product of H + i K with itself
+// pairwise), and weighted with w_q F(|k|, rho_q) / NI^3, summed over radial points and
+// classes in FP64.
 template <typename T, int N, int NI, int CH>
 __global__ __launch_bounds__(256) void dealias_gain_kernel(DealiasArgs a) {
     constexpr int NP = NI / CH;
@@ -95,17 +99,18 @@ __global__ __launch_bounds__(256) void dealias_gain_kernel(DealiasArgs a) {
         const int cl = a.gterms[2 * (g0 + gi)], ft = a.gterms[2 * (g0 + gi) + 1];
         const T* Ft = F + int64_t(ft) * a.nrho * a.K2 + k2;
         for (int q = 0; q < a.nrho; ++q) {
-            cx<T> Zv[4];
+            cx<T> Zv[3];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const cx<T>* Pb = P + ((int64_t(b) * 4 * a.ncls + v * a.ncls + cl) * a.nrho + q) * (CH * PCHF) + eP;
+            for (int v = 0; v < 3; ++v) {
+                const cx<T>* Pb = P + ((int64_t(b) * 3 * a.ncls + v * a.ncls + cl) * a.nrho + q) * (CH * PCHF) + eP;
                 cx<T> Z = Pb[0];
 #pragma unroll
                 for (int c = 1; c < CH; ++c) cmac(Z, tw[kx * CH + c], Pb[c * PCHF]);
                 Zv[v] = Z;
             }
-            const double zx = double(Zv[0].x) + double(Zv[1].x) - double(Zv[2].y) - double(Zv[3].y);
-            const double zy = double(Zv[0].y) + double(Zv[1].y) + double(Zv[2].x) + double(Zv[3].x);
+            // Z_HH - Z_KK + i (Z_SS - Z_HH - Z_KK)
+            const double zx = double(Zv[0].x) - double(Zv[1].x) - double(Zv[2].y) + double(Zv[0].y) + double(Zv[1].y);
+            const double zy = double(Zv[0].y) - double(Zv[1].y) + double(Zv[2].x) - double(Zv[0].x) - double(Zv[1].x);
             const double fq = double(Ft[int64_t(q) * a.K2]);
             ax = fma(fq, zx, ax);
             ay = fma(fq, zy, ay);
@@ -203,9 +208,9 @@ hipError_t run_dealiased(const dgfs_plan& outer, const dgfs_plan& inner, const T
     };
     cx<T>* fN = carve(int64_t(nb) * s * N3);
     cx<T>* fhI = carve(int64_t(nb) * s * NI3);
-    cx<T>* fHK = carve(int64_t(nb) * 2 * s * NI3);
+    cx<T>* fHK = carve(int64_t(nb) * 3 * s * NI3);
     cx<T>* fI = carve(int64_t(nb) * s * NI3);
-    cx<T>* P = carve(int64_t(nb) * 4 * ncls * inner.nrho * NI3);
+    cx<T>* P = carve(int64_t(nb) * 3 * ncls * inner.nrho * NI3);
     cx<T>* nu = carve(int64_t(nb) * ss.nslots * NI3);
     cx<T>* G = carve(int64_t(nb) * ss.nslots * N3);
     const char* dev = static_cast<const char*>(inner.dev);
@@ -220,7 +225,7 @@ hipError_t run_dealiased(const dgfs_plan& outer, const dgfs_plan& inner, const T
     if ((e = fft3d<T, NI>(fI, nullptr, int64_t(nb) * s, +1, T(1), st)) != hipSuccess) return e;
     mark(1);
 
-    // the gain over the split fields: 2s fields per node, 4 ncls sub-classes
+    // the gain over the split fields: 3s fields per node, 3 ncls sub-classes
     const char* ddev = static_cast<const char*>(outer.dealias_dev);
     GainArgs<T> ga;
     ga.fhat = fHK;
@@ -231,11 +236,11 @@ hipError_t run_dealiased(const dgfs_plan& outer, const dgfs_plan& inner, const T
     ga.nyq = reinterpret_cast<const T*>(dev + inner.off_nyq);
     ga.cls = reinterpret_cast<const int*>(ddev + outer.off_cls4);
     ga.wdir = reinterpret_cast<const T*>(ddev + outer.off_w4);
-    ga.s = 2 * s;
-    ga.ncls = 4 * ncls;
+    ga.s = 3 * s;
+    ga.ncls = 3 * ncls;
     ga.nrho = inner.nrho;
     ga.nb = nb;
-    const int64_t groups = ((nb + 7) / 8) * 8 * int64_t(4 * ncls) * inner.nrho * CH;
+    const int64_t groups = ((nb + 7) / 8) * 8 * int64_t(3 * ncls) * inner.nrho * CH;
     gain_kernel<T, NI, CH, CZ, PIPE, false, GAIN_COMPLEX>
         <<<dim3(unsigned(groups)), dim3(GainK<T, NI, CH, CZ>::NT), 0, st>>>(ga);
     if ((e = hipGetLastError()) != hipSuccess) return e;
