@@ -125,10 +125,13 @@ def grown_capacity(cap: int, need: int) -> int:
 class DeviceBackend:
     """Pools of device-resident slots on the HIP device (torch memory, libdgfs kernels)."""
 
-    def __init__(self, tile=None):
+    def __init__(self, tile=None, scheme: str = "euler"):
         import torch
+        if scheme not in ("euler", "ssprk2"):
+            raise ValueError("scheme is 'euler' or 'ssprk2'")
         self.torch = torch
         self.tile = tile
+        self.scheme = scheme
         self.plans = {}
 
     def plan(self, key):
@@ -151,6 +154,7 @@ class DevicePool:
     def __init__(self, backend: DeviceBackend, key):
         self.torch = backend.torch
         self.plan = backend.plan(key)
+        self.scheme = backend.scheme
         self.dt = key[2]
         self.s, self.N = self.plan.s, self.plan.N
         self.stream = self.torch.cuda.Stream()
@@ -159,10 +163,17 @@ class DevicePool:
         self.cap = 0
         self._staged = []          # pinned host buffers whose copies are in flight
 
+    def _ws_bytes(self, cap: int) -> int:
+        """Collide workspace for WS_NODES nodes per pass; SSP-RK2 adds its two stage states."""
+        ws = self.plan.workspace_bytes(min(cap, WS_NODES))
+        if self.scheme == "ssprk2":
+            ws += 2 * (((cap * self.s * self.N ** 3 * 4) + 255) // 256 * 256)
+        return ws
+
     def bytes_for(self, cap: int) -> int:
         if cap == 0:
             return 0
-        return cap * state_bytes(self.N, self.s) + self.plan.workspace_bytes(min(cap, WS_NODES))
+        return cap * state_bytes(self.N, self.s) + self._ws_bytes(cap)
 
     def resize(self, cap: int, live: int) -> None:
         torch = self.torch
@@ -177,7 +188,7 @@ class DevicePool:
                 f[:live].copy_(self.f[:live])
             self.f = f
             self.Q = torch.empty(shape, dtype=torch.float32, device="cuda")
-            self.ws = torch.empty(self.plan.workspace_bytes(min(cap, WS_NODES)), dtype=torch.uint8, device="cuda")
+            self.ws = torch.empty(self._ws_bytes(cap), dtype=torch.uint8, device="cuda")
         self.cap = cap
 
     def insert(self, slot: int, staged) -> None:
@@ -195,10 +206,14 @@ class DevicePool:
         return out
 
     def launch(self, n: int) -> None:
-        """One Euler step of slots [0, n) on this pool's stream; an event marks its end."""
+        """One step (forward Euler, or SSP-RK2 through dgfs_relax) of slots [0, n) on this
+        pool's stream; an event marks its end."""
         f, Q = self.f[:n], self.Q[:n]
-        self.plan.collide(f, out=Q, workspace=self.ws, stream=self.stream)
-        self.plan.relax_step(f, Q, self.dt, stream=self.stream)
+        if self.scheme == "ssprk2":
+            self.plan.relax(f, self.dt, 1, scheme="ssprk2", workspace=self.ws, stream=self.stream)
+        else:
+            self.plan.collide(f, out=Q, workspace=self.ws, stream=self.stream)
+            self.plan.relax_step(f, Q, self.dt, stream=self.stream)
         self.event = self.torch.cuda.Event()
         self.event.record(self.stream)
 
@@ -227,9 +242,9 @@ class Pool:
 
 
 class Server:
-    def __init__(self, backend=None, budget_bytes=None, keep_final=False, tile=None):
+    def __init__(self, backend=None, budget_bytes=None, keep_final=False, tile=None, scheme="euler"):
         if backend is None:
-            backend = DeviceBackend(tile=tile)
+            backend = DeviceBackend(tile=tile, scheme=scheme)
         if budget_bytes is None:
             import torch
             free, _ = torch.cuda.mem_get_info()
@@ -386,6 +401,8 @@ def main():
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--budget-gb", type=float, default=None)
+    ap.add_argument("--scheme", choices=["euler", "ssprk2"], default="euler",
+                    help="time step of every request: forward Euler or SSP-RK2 (Sec. 5)")
     ap.add_argument("--relaxed", action="store_true",
                     help="after the trace, serve a second one at 0.7x the measured capacity")
     args = ap.parse_args()
@@ -396,7 +413,7 @@ def main():
     budget = int(args.budget_gb * (1 << 30)) if args.budget_gb else None
     results = []
     trace = make_trace(args.requests, args.rate, args.seed, args.steps)
-    srv = Server(budget_bytes=budget)
+    srv = Server(budget_bytes=budget, scheme=args.scheme)
     staged, setup = srv.warm(trace)
     log(f"{len(srv.pools)} plans built and {len(trace)} requests staged in {setup:.1f} s")
     res = srv.run(trace, staged, progress=log)
@@ -415,7 +432,8 @@ def main():
         log(json.dumps(res2))
     print(json.dumps({
         "workload": "Poisson arrivals; 2-3 species with masses from {1,2,4,20}; N in {16,24,32,48}; "
-                    "L=6, M=12, N_rho=N/2, VHS omega=0.74; forward Euler dt=0.01 with the FP64 projection",
+                    "L=6, M=12, N_rho=N/2, VHS omega=0.74; " + ("forward Euler" if args.scheme == "euler" else "SSP-RK2")
+                    + " dt=0.01 with the FP64 projection",
         "steps_per_request": args.steps, "dtype": "f32 (FP64 projection)", "runs": results}), flush=True)
 
 

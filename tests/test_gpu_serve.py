@@ -53,3 +53,31 @@ def test_alone_equals_in_mix_and_follows_oracle():
             assert np.abs(got[i] - f[i]).max() <= 1e-5 * np.abs(f[i]).max()
         checked += 1
     assert checked == 2
+
+
+def test_ssprk2_serving_follows_oracle():
+    """Serving with SSP-RK2 steps (dgfs_relax per pool step): four N = 16 requests of 3
+    steps served together; two follow the oracle's SSP-RK2 trajectory of the projected
+    operator within 1e-5 relative L-inf, and each equals its result alone bit for bit."""
+    _require_gpu()
+    from paper_1903_03056_amd import serve as S
+    from oracle import stepping as OT
+    print("[case] serve ssprk2", flush=True)
+    trace = S.make_trace(4, 1e6, 31, steps=3, Ns=(16,))
+    backend = S.DeviceBackend(scheme="ssprk2")
+    mix = S.Server(backend=backend, budget_bytes=8 << 30, keep_final=True)
+    staged, _ = mix.warm(trace)
+    mix.run(trace, staged, realtime=False)
+    finals = {r.rid: r.final for r in trace}
+    for r in trace:
+        alone = S.Server(backend=backend, budget_bytes=8 << 30, keep_final=True)
+        r.final = None
+        alone.run([r], {r.rid: staged[r.rid]}, realtime=False)
+        np.testing.assert_array_equal(r.final, finals[r.rid], err_msg=f"request {r.rid}")
+    for r in trace[:2]:
+        prob = OS.vhs_problem(r.masses, S.OMEGA, S.L_BOX, r.N, S.M_DESIGN, r.N // 2)
+        rhs = OT.collision_rhs(prob)
+        f = OT.ssprk2(S.initial_state(r).astype(np.float32).astype(np.float64), rhs, r.dt, r.steps)
+        got = finals[r.rid].astype(np.float64)
+        for i in range(len(r.masses)):
+            assert np.abs(got[i] - f[i]).max() <= 1e-5 * np.abs(f[i]).max()
