@@ -429,7 +429,8 @@ def main():
                     help="leave out the plain per-point FP64 comparison leg (not part of the timed step)")
     ap.add_argument("--no-extra", action="store_true",
                     help="leave out the uneven-batch, species-grid, SSP-RK2 and measured-ceiling legs")
-    ap.add_argument("--only-leg", choices=["vss_slab", "dg_slab", "dealiased_slab"], default=None,
+    ap.add_argument("--only-leg", choices=["vss_slab", "dg_slab", "dealiased_slab", "uneven_group_graph",
+                                           "heavy_light_species_grids"], default=None,
                     help="run only the named extra workload and print its JSON (for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain device copy of 2 x 256 MiB first (calibrates HBM byte counters)")
@@ -448,6 +449,14 @@ def main():
     if args.only_leg == "vss_slab":
         log("VSS kernels only")
         print(json.dumps({"vss_slab": vss_leg(torch, torch.device("cuda:0"), args.steps)}), flush=True)
+        return
+    if args.only_leg == "uneven_group_graph":
+        log("uneven batch only")
+        print(json.dumps({args.only_leg: group_leg(torch, torch.device("cuda:0"), args.steps)[0]}), flush=True)
+        return
+    if args.only_leg == "heavy_light_species_grids":
+        log("heavy/light species grids only")
+        print(json.dumps({args.only_leg: species_grid_leg(torch, torch.device("cuda:0"), args.steps)[0]}), flush=True)
         return
     if args.only_leg in ("dg_slab", "dealiased_slab"):
         w = WORKLOAD
