@@ -272,8 +272,8 @@ def vss_leg(torch, dev, calls):
            "value": round(w["batch"] * s * s / (ms_call * 1e-3), 1), "unit": "evals/s", "calls": calls,
            "ms_per_call": round(ms_call, 3),
            "stages_ms": {"forward_fft": round(stage[0], 4), "gain": round(stage[1], 4),
-                         "radial_loss": round(stage[2], 4), "inverse_fft": round(stage[3], 4),
-                         "combine": round(stage[4], 4)},
+                         "radial_loss": round(stage[2], 4), "inverse_xy": round(stage[3], 4),
+                         "inverse_z_combine": round(stage[4], 4)},
            "gain_tflops": round(flops / (stage[1] * 1e-3) / 1e12, 2),
            "roofline": {
                "gain": {"bound": "alu", "achieved": round(flops / (stage[1] * 1e-3) / 1e12, 3),
@@ -553,8 +553,8 @@ def main():
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
                        "p99": round(float(np.percentile(step_ms, 99)), 4)},
         "stages_ms": {"forward_fft": round(stage_avg[0], 4), "gain": round(stage_avg[1], 4),
-                      "radial_loss": round(stage_avg[2], 4), "inverse_fft": round(stage_avg[3], 4),
-                      "combine": round(stage_avg[4], 4), "conserve_fp64": round(cons_avg, 4)},
+                      "radial_loss": round(stage_avg[2], 4), "inverse_xy": round(stage_avg[3], 4),
+                      "inverse_z_combine": round(stage_avg[4], 4), "conserve_fp64": round(cons_avg, 4)},
         "roofline": {"bound": "alu", "kernel": "gain_kernel", "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),

@@ -135,7 +135,8 @@ dgfs_status dgfs_collide(const dgfs_plan* plan, const void* f, void* Q, int64_t 
  * around each stage, the call waits for the work to finish, and stage_ms[0..4]
  * receives the summed durations (over batch slices) of: the forward transform of f,
  * the gain kernel (the sigma/rho loop of Sec. 4), the radial-sum and loss-spectrum
- * kernel, the inverse transforms, and the final combination.  Synchronous. */
+ * kernel, the x- and y-passes of the inverse transforms, and their z-pass fused with
+ * the final combination.  Synchronous. */
 dgfs_status dgfs_collide_timed(const dgfs_plan* plan, const void* f, void* Q, int64_t batch,
                                void* workspace, size_t ws_bytes, void* stream, float* stage_ms);
 

@@ -823,8 +823,8 @@ template <typename T>
 struct RadialArgs {
     const cx<T>* P;
     const cx<T>* fhat;
-    cx<T>* Gt;          // [nb][nslots][N^3]
-    cx<T>* Lt;          // [nb][nslots][N^3]
+    cx<T>* Gt;          // [nb][nslots][N][N][N/2+1]  gain spectrum, the k_z <= N/2 half
+    cx<T>* Lt;          // [nb][nslots][N][N][N/2+1]  loss spectrum, the same half
     const T* F;         // [nftab][nrho][K2]  w_q F(|k|, rho_q) / N^3
     const cx<T>* Fv;    // VSS: [nftab][nrho][2 directions][2][N][N][N/2+1]  F_H, F_A: the Hermitian and
                         //      anti-Hermitian parts (in the index sense) of w_q w_sigma F / N^3
@@ -842,8 +842,9 @@ struct RadialArgs {
 // representative with k_z <= N/2 (the stored half of the partials), forms
 // Q_hat+(k) = sum_terms sum_q w_q F(|k|, rho_q)/N^3 DFT(S_q)(k) and the loss spectrum
 // L(k) = sum_j G-(|k|) f_hat^j(k) for the CH x-modes k_x = k_xp + j N/CH, and writes
-// both at k and their conjugates at -k (S_q and f are real, F and G- are real and even
-// in k).  Pairs with k_z = 0 or N/2 lie wholly in the stored half and are written once.
+// both to the k_z <= N/2 half of the output spectra: the spectra are Hermitian (S_q and
+// f are real, F and G- are real and even in k), and the inverse transform takes them as
+// such.
 // VSS: each class (up to two directions) partial is the whole spectrum Z of
 // Re S_0 + i Re S_1; the thread reads Z at k and -k and adds the Nyquist-plane terms
 // (vss_accumulate).
@@ -952,20 +953,12 @@ __global__ __launch_bounds__(256) void radial_kernel(RadialArgs<T> a) {
             lac[j].y = fma(gm, v.y, lac[j].y);
         }
     }
-    const int64_t ob = (int64_t(b) * a.nslots + slot) * N3;
-    const bool mirror = kz != 0 && kz != N / 2;
-    const int ky2 = (N - ky) % N, kz2 = (N - kz) % N;
+    const int64_t ob = (int64_t(b) * a.nslots + slot) * (N2 * KZH);
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
-        const int kx = kxp + j * NP;
-        const int64_t o = ob + kx * N2 + ky * N + kz;
+        const int64_t o = ob + (int64_t(kxp + j * NP) * N + ky) * KZH + kz;
         a.Gt[o] = cx<T>{T(acc[j].x), T(acc[j].y)};
         a.Lt[o] = lac[j];
-        if (mirror) {
-            const int64_t o2 = ob + ((N - kx) % N) * N2 + ky2 * N + kz2;
-            a.Gt[o2] = cx<T>{T(acc[j].x), T(-acc[j].y)};
-            a.Lt[o2] = cx<T>{lac[j].x, -lac[j].y};
-        }
     }
 }
 
@@ -1070,8 +1063,6 @@ __global__ __launch_bounds__(256) void radial_vss_kernel(RadialArgs<T> a) {
         }
     }
 
-    const bool mirror = kz != 0 && kz != N / 2;
-    const int ky2 = (N - ky) % N, kz2 = (N - kz) % N;
     int k2[CH];
     auto sq = [](int k) {
         const int mk = k < N / 2 ? k : k - N;
@@ -1103,37 +1094,79 @@ __global__ __launch_bounds__(256) void radial_vss_kernel(RadialArgs<T> a) {
                     lac[j].y = fma(gm, v.y, lac[j].y);
                 }
             }
-            const int64_t ob = (int64_t(b) * a.nslots + sl) * N3;
+            const int64_t ob = (int64_t(b) * a.nslots + sl) * (N2 * KZH);
 #pragma unroll
             for (int j = 0; j < CH; ++j) {
-                const int kx = kxp + j * NP;
-                const int64_t o = ob + kx * N2 + ky * N + kz;
+                const int64_t o = ob + (int64_t(kxp + j * NP) * N + ky) * KZH + kz;
                 a.Gt[o] = cx<T>{T(acc[u][sl][j].x), T(acc[u][sl][j].y)};
                 a.Lt[o] = lac[j];
-                if (mirror) {
-                    const int64_t o2 = ob + ((N - kx) % N) * N2 + ky2 * N + kz2;
-                    a.Gt[o2] = cx<T>{T(acc[u][sl][j].x), T(-acc[u][sl][j].y)};
-                    a.Lt[o2] = cx<T>{lac[j].x, -lac[j].y};
-                }
             }
         }
     }
 }
 
-// ============================================================ combine kernel
-template <typename T>
-__global__ __launch_bounds__(256) void combine_kernel(const cx<T>* __restrict__ Gt, const cx<T>* __restrict__ Lt,
-                                                      const T* __restrict__ f, T* __restrict__ Q,
-                                                      const int* __restrict__ slots, int nslots, int s,
-                                                      int64_t n3, int64_t total) {
-    const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (t >= total) return;
-    const int64_t n = t % n3;
-    const int64_t bs = t / n3;
+// ====================================================== inverse transform + combine
+// The inverse transform of the gain and loss spectra (Hermitian, the k_z <= N/2 half
+// stored): the x- and y-passes run on the half in place (half_pass_kernel); the z-pass
+// restores each row's conjugate half, transforms it and keeps the real part, fused with
+// the combination Q = g - f_i l of the slot's species i (zpass_combine_kernel).
+template <typename T, int N, int AXIS>
+__global__ __launch_bounds__(256) void half_pass_kernel(cx<T>* data, int64_t npencils) {
+    constexpr int KZH = N / 2 + 1;
+    constexpr int64_t NH = int64_t(N) * N * KZH;
+    const int64_t pid = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (pid >= npencils) return;
+    const int64_t field = pid / (N * KZH);
+    const int r = int(pid - field * (N * KZH));
+    int64_t base, stride;
+    if constexpr (AXIS == 0) {  // r = (k_y, k_z)
+        base = field * NH + r;
+        stride = int64_t(N) * KZH;
+    } else {                    // r = (x, k_z)
+        base = field * NH + int64_t(r / KZH) * (N * KZH) + (r % KZH);
+        stride = KZH;
+    }
+    cx<T> v[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = data[base + k * stride];
+    fft<N, +1>(v);
+#pragma unroll
+    for (int k = 0; k < N; ++k) data[base + k * stride] = v[k];
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void zpass_combine_kernel(const cx<T>* __restrict__ Gh,
+                                                            const cx<T>* __restrict__ Lh, const T* __restrict__ f,
+                                                            T* __restrict__ Q, const int* __restrict__ slots,
+                                                            int nslots, int s, int64_t nrows) {
+    constexpr int KZH = N / 2 + 1;
+    constexpr int64_t N2 = int64_t(N) * N, N3 = N2 * N;
+    const int64_t row = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (row >= nrows) return;
+    const int64_t bs = row / N2;         // (node, slot)
+    const int64_t xy = row - bs * N2;
     const int slot = int(bs % nslots);
     const int64_t b = bs / nslots;
     const int sp = slots[5 * slot];
-    Q[t] = Gt[t].x - f[(b * s + sp) * n3 + n] * Lt[t].x;
+    const cx<T>* g = Gh + row * KZH;
+    const cx<T>* l = Lh + row * KZH;
+    cx<T> vg[N], vl[N];
+#pragma unroll
+    for (int k = 0; k < KZH; ++k) {
+        vg[k] = g[k];
+        vl[k] = l[k];
+    }
+#pragma unroll
+    for (int k = KZH; k < N; ++k) {
+        vg[k] = cx<T>{vg[N - k].x, -vg[N - k].y};
+        vl[k] = cx<T>{vl[N - k].x, -vl[N - k].y};
+    }
+    fft<N, +1>(vg);
+    fft<N, +1>(vl);
+    const T* fr = f + (b * s + sp) * N3 + xy * N;
+    T* q = Q + bs * N3 + xy * N;
+#pragma unroll
+    for (int z = 0; z < N; ++z) q[z] = vg[z].x - fr[z] * vl[z].x;
 }
 
 namespace detail {
@@ -1141,7 +1174,7 @@ namespace detail {
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // ev (optional): 6 events recorded at the stage boundaries (start, after forward FFT,
-// after gain, after radial, after inverse FFTs, after combine).
+// after gain, after radial, after the inverse x/y passes, after the z-pass + combine).
 template <typename T, int N, int CH, int CZ, bool PIPE, bool PACK, bool VSS>
 hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, bool pairs, hipStream_t st,
                      hipEvent_t* ev) {
@@ -1165,8 +1198,9 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
         Vn = reinterpret_cast<cx<T>*>(w);
         w += align256(sizeof(cx<T>) * int64_t(nb) * ncls * p.nrho * 3 * N * N);
     }
+    constexpr int64_t NH = int64_t(N) * N * (N / 2 + 1);  // stored half of a spectrum
     cx<T>* Gt = reinterpret_cast<cx<T>*>(w);
-    cx<T>* Lt = Gt + int64_t(nb) * ss.nslots * N3;  // contiguous with Gt
+    cx<T>* Lt = Gt + int64_t(nb) * ss.nslots * NH;  // contiguous with Gt
 
     const char* dev = static_cast<const char*>(p.dev);
     mark(0);
@@ -1239,13 +1273,17 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
     if ((e = hipGetLastError()) != hipSuccess) return e;
     mark(3);
 
-    e = fft3d<T, N>(Gt, nullptr, 2 * int64_t(nb) * ss.nslots, +1, T(1), st);
-    if (e != hipSuccess) return e;
+    {
+        const int64_t np = 2 * int64_t(nb) * ss.nslots * N * (N / 2 + 1);
+        half_pass_kernel<T, N, 0><<<dim3(unsigned((np + 255) / 256)), dim3(256), 0, st>>>(Gt, np);
+        half_pass_kernel<T, N, 1><<<dim3(unsigned((np + 255) / 256)), dim3(256), 0, st>>>(Gt, np);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     mark(4);
 
-    const int64_t total = int64_t(nb) * ss.nslots * N3;
-    combine_kernel<T><<<dim3(unsigned((total + 255) / 256)), dim3(256), 0, st>>>(
-        Gt, Lt, f, Q, ra.slots, ss.nslots, p.s, N3, total);
+    const int64_t rows = int64_t(nb) * ss.nslots * N * N;
+    zpass_combine_kernel<T, N><<<dim3(unsigned((rows + 255) / 256)), dim3(256), 0, st>>>(
+        Gt, Lt, f, Q, ra.slots, ss.nslots, p.s, rows);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     mark(5);
     return hipSuccess;

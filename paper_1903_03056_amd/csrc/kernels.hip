@@ -9,9 +9,10 @@
 //                        B_p = IDFT(f_hat^j e^{-i pi rho b m.sigma_p / L})  (= f^j(v - b rho sigma_p)),
 //                      then the partial forward DFT of S_q over the chunk  -> P
 //   3. radial_kernel   Q_hat+ = sum_terms sum_q w_q F(|k|, rho_q) / N^3 * DFT(S_q)
-//                      L_hat  = sum_j G-_ij(|k|) f_hat^j                    -> Gt, Lt
-//   4. fft_pass x3     inverse DFT of Gt and Lt (unnormalised)
-//   5. combine         Q = Re(IDFT Gt) - f^i Re(IDFT Lt)
+//                      L_hat  = sum_j G-_ij(|k|) f_hat^j          -> Gt, Lt (k_z <= N/2 half)
+//   4. half_pass x2    inverse DFT of Gt and Lt along x and y, on the stored half
+//   5. zpass_combine   inverse DFT along z (Hermitian rows, real result) fused with
+//                      Q = IDFT(Gt) - f^i IDFT(Lt)
 //
 // The sigma-sum is taken before the forward transform of the gain because, for the
 // VHS family, F(k, rho, sigma) does not depend on sigma; with an antipodal design the
