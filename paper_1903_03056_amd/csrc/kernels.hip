@@ -32,16 +32,20 @@ namespace dgfs {
 // (3 rows), m_i h_i^3 |v|^2 (1 row), on species i's own grid (half-width Ls[i]).
 // With UPDATE, the projected value is not stored but added to the state:
 // f <- f + dt * Q_projected (forward-Euler step of a homogeneous relaxation).
-template <typename TIN, bool UPDATE>
+// The grid size is a template argument for the compiled N (NC > 0), so the index
+// arithmetic of the velocity coordinates uses constant divisors; NC = 0 reads it from Nrt.
+template <typename TIN, bool UPDATE, int NC>
 __global__ __launch_bounds__(1024) void conserve_kernel(const TIN* Q, double* out, TIN* fstate, double dt,
                                                         const double* __restrict__ Minv,
                                                         const double* __restrict__ mass,
-                                                        const double* __restrict__ Ls, int s, int N) {
+                                                        const double* __restrict__ Ls, int s, int Nrt) {
     constexpr int R = 12;  // s + 4 <= 12
     __shared__ double red[16][R];
     __shared__ double lam[R];
+    const int N = NC > 0 ? NC : Nrt;
     const int b = blockIdx.x;
-    const int64_t n3 = int64_t(N) * N * N, tot = int64_t(s) * n3;
+    const int n3 = N * N * N;
+    const int64_t tot = int64_t(s) * n3;
     const TIN* q = Q + int64_t(b) * tot;
     double* o = UPDATE ? nullptr : out + int64_t(b) * tot;
     TIN* fs = UPDATE ? fstate + int64_t(b) * tot : nullptr;
@@ -49,20 +53,27 @@ __global__ __launch_bounds__(1024) void conserve_kernel(const TIN* Q, double* ou
     double acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = 0.0;
-    for (int64_t idx = threadIdx.x; idx < tot; idx += 1024) {
-        const int i = int(idx / n3);
-        const int n = int(idx - int64_t(i) * n3);
-        const double L = Ls[i], h = 2.0 * L / N, h3 = h * h * h;
-        const double vx = -L + (n / (N * N)) * h, vy = -L + ((n / N) % N) * h, vz = -L + (n % N) * h;
-        const double val = double(q[idx]);
-        const double mh = mass[i] * h3 * val;
+    for (int i = 0; i < s; ++i) {
+        const double L = Ls[i], h = 2.0 * L / N;
+        const TIN* qi = q + int64_t(i) * n3;
+        double a0 = 0.0, ax = 0.0, ay = 0.0, az = 0.0, ae = 0.0;
+        for (int n = threadIdx.x; n < n3; n += 1024) {
+            const double vx = -L + (n / (N * N)) * h, vy = -L + ((n / N) % N) * h, vz = -L + (n % N) * h;
+            const double val = double(qi[n]);
+            a0 += val;
+            ax = fma(val, vx, ax);
+            ay = fma(val, vy, ay);
+            az = fma(val, vz, az);
+            ae = fma(val, vx * vx + vy * vy + vz * vz, ae);
+        }
+        const double h3 = h * h * h, mh = mass[i] * h3;
 #pragma unroll
         for (int r = 0; r < R - 4; ++r)
-            if (r == i) acc[r] += h3 * val;
-        acc[R - 4] += mh * vx;
-        acc[R - 3] += mh * vy;
-        acc[R - 2] += mh * vz;
-        acc[R - 1] += mh * (vx * vx + vy * vy + vz * vz);
+            if (r == i) acc[r] = h3 * a0;
+        acc[R - 4] = fma(mh, ax, acc[R - 4]);
+        acc[R - 3] = fma(mh, ay, acc[R - 3]);
+        acc[R - 2] = fma(mh, az, acc[R - 2]);
+        acc[R - 1] = fma(mh, ae, acc[R - 1]);
     }
     // block reduction
 #pragma unroll
@@ -93,19 +104,20 @@ __global__ __launch_bounds__(1024) void conserve_kernel(const TIN* Q, double* ou
         }
     }
     __syncthreads();
-    for (int64_t idx = threadIdx.x; idx < tot; idx += 1024) {
-        const int i = int(idx / n3);
-        const int n = int(idx - int64_t(i) * n3);
-        const double L = Ls[i], h = 2.0 * L / N, h3 = h * h * h;
-        const double vx = -L + (n / (N * N)) * h, vy = -L + ((n / N) % N) * h, vz = -L + (n % N) * h;
-        const double mh = mass[i] * h3;
-        const double corr = lam[i] * h3 + mh * (lam[s] * vx + lam[s + 1] * vy + lam[s + 2] * vz +
-                                                lam[s + 3] * (vx * vx + vy * vy + vz * vz));
-        const double v = double(q[idx]) - corr;
-        if constexpr (UPDATE)
-            fs[idx] = TIN(double(fs[idx]) + dt * v);
-        else
-            o[idx] = v;
+    for (int i = 0; i < s; ++i) {
+        const double L = Ls[i], h = 2.0 * L / N, h3 = h * h * h, mh = mass[i] * h3;
+        const double c0 = lam[i] * h3, cx_ = mh * lam[s], cy = mh * lam[s + 1], cz = mh * lam[s + 2],
+                     ce = mh * lam[s + 3];
+        const int64_t off = int64_t(i) * n3;
+        for (int n = threadIdx.x; n < n3; n += 1024) {
+            const double vx = -L + (n / (N * N)) * h, vy = -L + ((n / N) % N) * h, vz = -L + (n % N) * h;
+            const double corr = c0 + cx_ * vx + cy * vy + cz * vz + ce * (vx * vx + vy * vy + vz * vz);
+            const double v = double(q[off + n]) - corr;
+            if constexpr (UPDATE)
+                fs[off + n] = TIN(double(fs[off + n]) + dt * v);
+            else
+                o[off + n] = v;
+        }
     }
 }
 
@@ -177,23 +189,28 @@ hipError_t launch_conserve(const dgfs_plan& p, const void* Q, double* out, void*
     const double* mass = minv + (p.s + 4) * (p.s + 4);
     const double* Ls = mass + p.s;
     const dim3 grid(static_cast<unsigned>(nb)), block(1024);
-    if (p.precision == DGFS_FP64) {
+    auto run = [&](auto tin, auto nc) {
+        using TIN = decltype(tin);
+        constexpr int NC = decltype(nc)::value;
         if (fstate)
-            conserve_kernel<double, true><<<grid, block, 0, st>>>(static_cast<const double*>(Q), nullptr,
-                                                                  static_cast<double*>(fstate), dt, minv, mass, Ls,
-                                                                  p.s, p.N);
+            conserve_kernel<TIN, true, NC><<<grid, block, 0, st>>>(static_cast<const TIN*>(Q), nullptr,
+                                                                   static_cast<TIN*>(fstate), dt, minv, mass, Ls,
+                                                                   p.s, p.N);
         else
-            conserve_kernel<double, false><<<grid, block, 0, st>>>(static_cast<const double*>(Q), out, nullptr, 0.0,
-                                                                   minv, mass, Ls, p.s, p.N);
-    } else {
-        if (fstate)
-            conserve_kernel<float, true><<<grid, block, 0, st>>>(static_cast<const float*>(Q), nullptr,
-                                                                 static_cast<float*>(fstate), dt, minv, mass, Ls,
-                                                                 p.s, p.N);
-        else
-            conserve_kernel<float, false><<<grid, block, 0, st>>>(static_cast<const float*>(Q), out, nullptr, 0.0,
-                                                                  minv, mass, Ls, p.s, p.N);
-    }
+            conserve_kernel<TIN, false, NC><<<grid, block, 0, st>>>(static_cast<const TIN*>(Q), out, nullptr, 0.0,
+                                                                    minv, mass, Ls, p.s, p.N);
+    };
+    auto by_n = [&](auto tin) {
+        switch (p.N) {
+            case 16: run(tin, std::integral_constant<int, 16>{}); break;
+            case 24: run(tin, std::integral_constant<int, 24>{}); break;
+            case 32: run(tin, std::integral_constant<int, 32>{}); break;
+            case 48: run(tin, std::integral_constant<int, 48>{}); break;
+            default: run(tin, std::integral_constant<int, 0>{}); break;
+        }
+    };
+    if (p.precision == DGFS_FP64) by_n(double{});
+    else by_n(float{});
     return hipGetLastError();
 }
 
