@@ -962,6 +962,26 @@ __global__ __launch_bounds__(256) void radial_kernel(RadialArgs<T> a) {
     }
 }
 
+// Row r (0 <= r < NP N) of the radial thread order, as the (k_xp, k_y) row of a chunk
+// partial, enumerated in mirror pairs: the groups k_xp = 0 and k_xp = NP/2 (each its own
+// mirror in k_xp; rows k_y and -k_y adjacent, 0 and N/2 first), then the rows of k_xp
+// and NP - k_xp for k_xp = 1 .. NP/2 - 1, each beside its mirror.  A thread reads the
+// partials at k and -k, so with this order a workgroup's reads of a row and of its
+// mirror row fall in the same cache lines at the same time.
+template <int N, int NP>
+__device__ __forceinline__ void mirror_paired_row(int r, int& kxp, int& ky) {
+    static_assert(NP % 2 == 0, "row pairing needs an even number of x-planes per chunk");
+    if (r < 2 * N) {
+        kxp = r < N ? 0 : NP / 2;
+        const int rr = r < N ? r : r - N, i = rr >> 1;
+        ky = (rr & 1) ? (i == 0 ? N / 2 : N - i) : i;
+        return;
+    }
+    const int g = (r - 2 * N) / (2 * N), rr = (r - 2 * N) % (2 * N), i = rr >> 1;
+    kxp = (rr & 1) ? NP - 1 - g : 1 + g;
+    ky = (rr & 1) ? (N - i) % N : i;
+}
+
 // VSS radial sum with every slot of NB nodes in one thread: per class (up to two
 // directions), use and radial point the table values are loaded once and applied to the
 // NB nodes' partials (read at k and -k; the second use of an unlike class finds them in
@@ -979,7 +999,9 @@ __global__ __launch_bounds__(256) void radial_vss_kernel(RadialArgs<T> a) {
     if (t >= ngroups * PCH) return;
     const int e = int(t % PCH);
     const int b0 = int(t / PCH) * NB;
-    const int kz = e % KZH, ky = (e / KZH) % N, kxp = e / (N * KZH);
+    const int kz = e % KZH;
+    int kxp, ky;
+    mirror_paired_row<N, NP>(e / KZH, kxp, ky);
     const int kxpm = (NP - kxp) % NP, kym = (N - ky) % N, kzm = (N - kz) % N;
     const int64_t eP = (int64_t(kxp) * N + ky) * N + kz, ePm = (int64_t(kxpm) * N + kym) * N + kzm;
     const int64_t fo = (int64_t(kxp) * N + ky) * KZH + kz;
