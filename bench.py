@@ -356,8 +356,8 @@ def slab_leg(torch, dev, plan, w, steps, dt=2e-4):
 
 def dealias_leg(torch, dev, f32, w, calls):
     """The slab workload with eq. (sum) read as a linear convolution (spectra zero-padded
-    to 3N/2 = 48, the gain over three sub-classes of the Hermitian parts of each padded
-    spectrum)."""
+    to 3N/2 = 48; the padded spectra are not Hermitian, so the gain transforms them
+    unpaired)."""
     from paper_1903_03056_amd import CollisionPlan
     s = len(w["masses"])
     plan = CollisionPlan(w["masses"], w["N"], w["L"], w["M"], w["n_rho"], omega=w["omega"], precision="f32",
@@ -383,13 +383,12 @@ def dealias_leg(torch, dev, f32, w, calls):
     return {"roofline_gain": {"bound": "alu", "achieved": round(flops / (stage[1] * 1e-3) / 1e12, 3),
                               "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                               "frac": round(flops / (stage[1] * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4),
-                              "flop_model": "the padded gain as one complex product per direction on 48^3 "
-                                            "(the three Hermitian sub-classes are overhead, not counted)"},
+                              "flop_model": "the padded gain as one complex product per direction on 48^3"},
             "workload": "the slab workload (256 nodes, N=32, M=12, N_rho=16, FP32) with the linear (dealiased) "
                         "convolution, padded to 48^3, 64-node workspace slices",
             "value": round(w["batch"] * s * s / (ms_call * 1e-3), 1), "unit": "evals/s", "calls": calls,
             "ms_per_call": round(ms_call, 3),
-            "stages_ms": {"forward_pad_split": round(stage[0], 3), "gain_48": round(stage[1], 3),
+            "stages_ms": {"forward_pad_interpolant": round(stage[0], 3), "gain_48": round(stage[1], 3),
                           "kept_modes_and_loss_spectrum": round(stage[2], 3),
                           "loss_product_and_inverse": round(stage[3], 3), "real_part": round(stage[4], 3)}}
 

@@ -742,7 +742,10 @@ size_t dgfs_plan::ws_per_node(bool pairs) const {
     const int nslots = pairs ? s * s : s;
     if (inner)
         return dgfs::dealias_ws_per_node(elem(), N, s, int(inner->classes.size()), inner->nrho, nslots);
-    return c * (size_t(s) + 2 * size_t(nslots)) + part * classes.size() * size_t(nrho);
+    // f_hat, the partials, and the gain and loss spectra of every slot (their k_z <= N/2
+    // halves: the spectra are Hermitian)
+    const size_t half = 2 * elem() * size_t(N) * N * (N / 2 + 1);
+    return c * size_t(s) + 2 * half * size_t(nslots) + part * classes.size() * size_t(nrho);
 }
 
 extern "C" {
@@ -810,28 +813,6 @@ dgfs_status dgfs_plan_create(const dgfs_problem* problem, dgfs_plan** out) {
         dgfs_plan_destroy(outer);
         return st;
     }
-    // sub-classes over the fields H_i (index i), K_i (index s + i) and H_i + K_i (index
-    // 2s + i) of the padded spectrum P = H + i K: HH, KK and (H+K)(H+K), whose partials
-    // combine as Z_HH - Z_KK + i (Z_(H+K)(H+K) - Z_HH - Z_KK)
-    const dgfs_plan& in = *outer->inner;
-    const int nc = int(in.classes.size()), s = in.s;
-    std::vector<int> cls4;
-    std::vector<double> w4;
-    for (int v = 0; v < 3; ++v)
-        for (const auto& c : in.classes) {
-            cls4.insert(cls4.end(), {v * s + c.i, v * s + c.j, c.ndir, c.dir_offset});
-            w4.push_back(c.weight);
-        }
-    std::vector<char> blob;
-    push_int(blob, outer->off_cls4, cls4);
-    if (outer->precision == DGFS_FP64) push_real<double>(blob, outer->off_w4, w4);
-    else push_real<float>(blob, outer->off_w4, w4);
-    (void)nc;
-    if (hipMalloc(&outer->dealias_dev, blob.size()) != hipSuccess ||
-        hipMemcpy(outer->dealias_dev, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
-        dgfs_plan_destroy(outer);
-        return fail(DGFS_ENOMEM, "upload of the dealiasing tables failed");
-    }
     *out = outer;
     return DGFS_OK;
 }
@@ -840,7 +821,6 @@ void dgfs_plan_destroy(dgfs_plan* plan) {
     if (!plan) return;
     for (auto& part : plan->parts) dgfs_plan_destroy(part.plan);
     if (plan->inner) dgfs_plan_destroy(plan->inner);
-    if (plan->dealias_dev) hipFree(plan->dealias_dev);
     if (plan->dev) hipFree(plan->dev);
     delete plan;
 }

@@ -1,9 +1,9 @@
 // The dealiased (linear-convolution) form of eq. (sum): l + m = k with l, m, k all in
 // [-N/2, N/2-1]^3, no wrap-around.  The spectra are zero-padded to NI = 3N/2 (l + m then
 // never wraps onto a kept mode), the gain runs on the NI grid with the whole complex
-// product kept (over the Hermitian parts of each padded spectrum), the loss product
-// f nu is taken on the NI grid, and the kept modes are synthesised on the N grid, whose
-// real part is the result.  Included by the vss_<NI>
+// product kept (the padded spectrum is not Hermitian, so its shifted fields come from
+// unpaired transforms), the loss product f nu is taken on the NI grid, and the kept modes
+// are synthesised on the N grid, whose real part is the result.  Included by the vss_<NI>
 // tile files, whose gain kernels keep the complex product.
 #pragma once
 
@@ -32,29 +32,6 @@ __global__ __launch_bounds__(256) void pad_kernel(const cx<T>* __restrict__ fN, 
     fI[t] = v;
 }
 
-// The padded spectrum P of a real field is not Hermitian on the NI grid (its modes with
-// a component -N/2 have no +N/2 partner), but the gain kernel's paired transforms assume
-// it.  Split exactly: P = H + i K with H(k) = (P(k) + conj P(-k))/2 and
-// K(k) = (P(k) - conj P(-k))/(2i), both Hermitian; out[b][i] = H_i, out[b][s + i] = K_i,
-// out[b][2s + i] = H_i + K_i.
-template <typename T, int NI>
-__global__ __launch_bounds__(256) void split_kernel(const cx<T>* __restrict__ P, cx<T>* __restrict__ out, int s,
-                                                    int64_t nfields) {
-    constexpr int64_t NI3 = int64_t(NI) * NI * NI;
-    const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (t >= nfields * NI3) return;
-    const int64_t fld = t / NI3;
-    const int e = int(t % NI3);
-    const int kx = e / (NI * NI), ky = (e / NI) % NI, kz = e % NI;
-    const int em = (((NI - kx) % NI) * NI + (NI - ky) % NI) * NI + (NI - kz) % NI;
-    const cx<T> p = P[t], pm = P[fld * NI3 + em];
-    const int64_t b = fld / s, i = fld % s;
-    const cx<T> h{T(0.5) * (p.x + pm.x), T(0.5) * (p.y - pm.y)}, k{T(0.5) * (p.y + pm.y), T(0.5) * (pm.x - p.x)};
-    out[(b * 3 * s + i) * NI3 + e] = h;
-    out[(b * 3 * s + s + i) * NI3 + e] = k;
-    out[(b * 3 * s + 2 * s + i) * NI3 + e] = cx<T>{h.x + k.x, h.y + k.y};
-}
-
 struct DealiasArgs {
     const void* P;       // [nb][ncls][nrho][CH][NI/CH][NI][NI] complex partials
     const void* fhatI;   // [nb][s][NI^3]
@@ -70,10 +47,8 @@ struct DealiasArgs {
 };
 
 // Kept gain modes: one thread per (node, slot, N-grid mode k): the chunk partials at the
-// NI index of k are combined, the three sub-classes of each class joined as
-// Z_HH - Z_KK + i (Z_(H+K)(H+K) - Z_HH - Z_KK) (= the product of H + i K with itself
-// pairwise), and weighted with w_q F(|k|, rho_q) / NI^3, summed over radial points and
-// classes in FP64.
+// NI index of k are combined and weighted with w_q F(|k|, rho_q) / NI^3, summed over
+// radial points and classes in FP64.
 template <typename T, int N, int NI, int CH>
 __global__ __launch_bounds__(256) void dealias_gain_kernel(DealiasArgs a) {
     constexpr int NP = NI / CH;
@@ -99,21 +74,13 @@ __global__ __launch_bounds__(256) void dealias_gain_kernel(DealiasArgs a) {
         const int cl = a.gterms[2 * (g0 + gi)], ft = a.gterms[2 * (g0 + gi) + 1];
         const T* Ft = F + int64_t(ft) * a.nrho * a.K2 + k2;
         for (int q = 0; q < a.nrho; ++q) {
-            cx<T> Zv[3];
+            const cx<T>* Pb = P + ((int64_t(b) * a.ncls + cl) * a.nrho + q) * (CH * PCHF) + eP;
+            cx<T> Z = Pb[0];
 #pragma unroll
-            for (int v = 0; v < 3; ++v) {
-                const cx<T>* Pb = P + ((int64_t(b) * 3 * a.ncls + v * a.ncls + cl) * a.nrho + q) * (CH * PCHF) + eP;
-                cx<T> Z = Pb[0];
-#pragma unroll
-                for (int c = 1; c < CH; ++c) cmac(Z, tw[kx * CH + c], Pb[c * PCHF]);
-                Zv[v] = Z;
-            }
-            // Z_HH - Z_KK + i (Z_SS - Z_HH - Z_KK)
-            const double zx = double(Zv[0].x) - double(Zv[1].x) - double(Zv[2].y) + double(Zv[0].y) + double(Zv[1].y);
-            const double zy = double(Zv[0].y) - double(Zv[1].y) + double(Zv[2].x) - double(Zv[0].x) - double(Zv[1].x);
+            for (int c = 1; c < CH; ++c) cmac(Z, tw[kx * CH + c], Pb[c * PCHF]);
             const double fq = double(Ft[int64_t(q) * a.K2]);
-            ax = fma(fq, zx, ax);
-            ay = fma(fq, zy, ay);
+            ax = fma(fq, double(Z.x), ax);
+            ay = fma(fq, double(Z.y), ay);
         }
     }
     static_cast<cx<T>*>(a.G)[t] = cx<T>{T(ax), T(ay)};
@@ -208,9 +175,8 @@ hipError_t run_dealiased(const dgfs_plan& outer, const dgfs_plan& inner, const T
     };
     cx<T>* fN = carve(int64_t(nb) * s * N3);
     cx<T>* fhI = carve(int64_t(nb) * s * NI3);
-    cx<T>* fHK = carve(int64_t(nb) * 3 * s * NI3);
     cx<T>* fI = carve(int64_t(nb) * s * NI3);
-    cx<T>* P = carve(int64_t(nb) * 3 * ncls * inner.nrho * NI3);
+    cx<T>* P = carve(int64_t(nb) * ncls * inner.nrho * NI3);
     cx<T>* nu = carve(int64_t(nb) * ss.nslots * NI3);
     cx<T>* G = carve(int64_t(nb) * ss.nslots * N3);
     const char* dev = static_cast<const char*>(inner.dev);
@@ -219,28 +185,26 @@ hipError_t run_dealiased(const dgfs_plan& outer, const dgfs_plan& inner, const T
     mark(0);
     if ((e = fft3d<T, N>(fN, f, int64_t(nb) * s, -1, T(1.0 / double(N3)), st)) != hipSuccess) return e;
     pad_kernel<T, N, NI><<<blocks_for(int64_t(nb) * s * NI3), 256, 0, st>>>(fN, fhI, int64_t(nb) * s);
-    split_kernel<T, NI><<<blocks_for(int64_t(nb) * s * NI3), 256, 0, st>>>(fhI, fHK, s, int64_t(nb) * s);
     if ((e = hipMemcpyAsync(fI, fhI, sizeof(cx<T>) * nb * s * NI3, hipMemcpyDeviceToDevice, st)) != hipSuccess)
         return e;
     if ((e = fft3d<T, NI>(fI, nullptr, int64_t(nb) * s, +1, T(1), st)) != hipSuccess) return e;
     mark(1);
 
-    // the gain over the split fields: 3s fields per node, 3 ncls sub-classes
-    const char* ddev = static_cast<const char*>(outer.dealias_dev);
+    // the gain over the padded spectra with the NI-grid plan's classes
     GainArgs<T> ga;
-    ga.fhat = fHK;
+    ga.fhat = fhI;
     ga.P = P;
     ga.PL = nullptr;
     ga.kx = reinterpret_cast<const cx<T>*>(dev + inner.off_kx);
     ga.yz = reinterpret_cast<const cx<T>*>(dev + inner.off_yz);
     ga.nyq = reinterpret_cast<const T*>(dev + inner.off_nyq);
-    ga.cls = reinterpret_cast<const int*>(ddev + outer.off_cls4);
-    ga.wdir = reinterpret_cast<const T*>(ddev + outer.off_w4);
-    ga.s = 3 * s;
-    ga.ncls = 3 * ncls;
+    ga.cls = reinterpret_cast<const int*>(dev + inner.off_cls);
+    ga.wdir = reinterpret_cast<const T*>(dev + inner.off_wdir);
+    ga.s = s;
+    ga.ncls = ncls;
     ga.nrho = inner.nrho;
     ga.nb = nb;
-    const int64_t groups = ((nb + 7) / 8) * 8 * int64_t(3 * ncls) * inner.nrho * CH;
+    const int64_t groups = ((nb + 7) / 8) * 8 * int64_t(ncls) * inner.nrho * CH;
     gain_kernel<T, NI, CH, CZ, PIPE, false, GAIN_COMPLEX>
         <<<dim3(unsigned(groups)), dim3(GainK<T, NI, CH, CZ>::NT), 0, st>>>(ga);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -19,7 +19,8 @@ namespace dgfs {
 // GAIN_REAL     Re S summed over the class's directions (VHS: F real and even in k);
 //               the Hermitian half of the partial is stored.
 // GAIN_COMPLEX  the complex S summed over the class's directions, whole spectrum stored
-//               (the dealiased form, whose inputs are not spectra of real fields).
+//               (the dealiased form, whose inputs are not spectra of real fields: the
+//               shifted fields come from unpaired transforms).
 // GAIN_VSS      VSS (F depends on sigma): a class holds at most two directions; their
 //               real parts are transformed together as Re S_0 + i Re S_1 (whole spectrum
 //               stored), and their imaginary parts, which reach the result only on the
@@ -189,11 +190,41 @@ __device__ __forceinline__ bool pencil_slot(int slot, int& ly, int& lz) {
 // f_hat(., P1) + i f_hat(., P2), whose output (a1 - b2) + i (b1 + a2) (b = -d (-1)^n / 2)
 // gives both.  That removes a round of the pass when N^2/2 + 2 slots would need one
 // more than N^2/2; only the wavefront holding those two slots loads two pencils.
-template <typename T, int N, int CH, int CZ, bool PIPE>
+//
+// With HERM = false the spectrum is that of a complex field (no pairing): every one of the
+// N^2 x-pencils is transformed and stored with its own y/z phase.
+template <typename T, int N, int CH, int CZ, bool PIPE, bool HERM = true>
 __device__ __forceinline__ void field_ifft(const cx<T>* __restrict__ fh, const cx<T>* __restrict__ kxt,
                                            const cx<T>* __restrict__ yzt, T nyq, int c, cx<T>* buf, int cz,
                                            int m, int r, cx<T>* out) {
     using K = GainK<T, N, CH, CZ>;
+    if constexpr (!HERM) {
+        constexpr int ES = int(sizeof(cx<T>));
+        constexpr int RS = N * N * ES;
+        const __amdgpu_buffer_rsrc_t rs = field_rsrc<T>(fh, N * RS);
+#pragma unroll 1
+        for (int k = 0; k < (N * N + K::NT - 1) / K::NT; ++k) {
+            const int P = int(threadIdx.x) + k * K::NT;
+            if ((N * N) % K::NT != 0 && P >= N * N) break;
+            const int ly = P / N, lz = P % N;
+            cx<T> y[K::NP];
+#pragma unroll
+            for (int l = 0; l < K::NP; ++l) y[l] = cx<T>{T(0), T(0)};
+#pragma unroll 1
+            for (int t = 0; t < CH; ++t) {
+#pragma unroll
+                for (int l = 0; l < K::NP; ++l) cmac(y[l], bload<T>(rs, P * ES, (l + t * K::NP) * RS), kxt[l + t * K::NP]);
+            }
+            fft<K::NP, +1>(y);
+            const cx<T> cyz = yzt[ly] * yzt[N + lz];
+#pragma unroll
+            for (int mm = 0; mm < K::NP; ++mm) buf[(mm * N + ly) * K::ROW + lz] = y[mm] * cyz;
+        }
+        __syncthreads();
+        yz_passes<T, N, CH, CZ, +1>(buf, cz, m, r, out);
+        __syncthreads();
+        return;
+    }
     constexpr int ROUNDS_ALL = (N * N / 2 + 2 + K::NT - 1) / K::NT;
     constexpr int ROUNDS_SELF = (N * N / 2 + K::NT - 1) / K::NT;
     constexpr bool SELF = ROUNDS_SELF < ROUNDS_ALL;
@@ -641,10 +672,11 @@ __global__ __launch_bounds__((GainK<T, N, CH, CZ>::NT)) void gain_kernel(GainArg
                                                  a.yz + (base + 1) * 2 * N, a.nyq[base + 1], c, buf, cz, m, r, w, Sd);
         } else {
             cx<T> A[K::NS], B[K::NS];
-            field_ifft<T, N, CH, CZ, PIPE>(fhi, a.kx + ((base + 0) * CH + c) * N, a.yz + (base + 0) * 2 * N,
-                                           a.nyq[base], c, buf, cz, m, r, A);
-            field_ifft<T, N, CH, CZ, PIPE>(fhj, a.kx + ((base + 1) * CH + c) * N, a.yz + (base + 1) * 2 * N,
-                                           a.nyq[base + 1], c, buf, cz, m, r, B);
+            constexpr bool HERM = MODE != GAIN_COMPLEX;
+            field_ifft<T, N, CH, CZ, PIPE, HERM>(fhi, a.kx + ((base + 0) * CH + c) * N, a.yz + (base + 0) * 2 * N,
+                                                 a.nyq[base], c, buf, cz, m, r, A);
+            field_ifft<T, N, CH, CZ, PIPE, HERM>(fhj, a.kx + ((base + 1) * CH + c) * N, a.yz + (base + 1) * 2 * N,
+                                                 a.nyq[base + 1], c, buf, cz, m, r, B);
 #pragma unroll
             for (int n = 0; n < K::NS; ++n) Sd[n] = fma(w, fma(A[n].x, B[n].x, -A[n].y * B[n].y), Sd[n]);
             if constexpr (MODE == GAIN_COMPLEX) {

@@ -98,10 +98,6 @@ struct dgfs_plan {
     // Dealiased form (linear convolution): the companion plan on the 3N/2 grid whose
     // tables the padded gain and loss use; this plan keeps the conservation tables.
     dgfs_plan* inner = nullptr;
-    // ... and the three sub-classes of each inner class over the split fields (below):
-    // [3][ncls][4] ints (i, j, ndir, dir_offset) then [3][ncls] weights (plan precision)
-    void* dealias_dev = nullptr;
-    size_t off_cls4 = 0, off_w4 = 0;
 
     size_t elem() const { return precision == DGFS_FP64 ? sizeof(double) : sizeof(float); }
     size_t n3() const { return size_t(N) * N * N; }
@@ -132,12 +128,11 @@ hipError_t launch_move(const dgfs_plan& p, const void* in, int64_t in_stride, vo
 hipError_t launch_axpby(const dgfs_plan& p, const void* x, const void* y, void* out, double a, double b, int64_t n,
                         hipStream_t stream);
 // Workspace bytes per node of the dealiased pipeline on an N-grid plan (NI = 3N/2):
-// f_hat on N, f_hat, its two Hermitian parts and their sum, and the complex interpolant
-// on NI, the partials of the three sub-classes on NI, the loss spectra on NI and the kept
-// modes on N.
+// f_hat on N, the padded f_hat and the complex interpolant on NI, the class partials on
+// NI, the loss spectra on NI and the kept modes on N.
 inline size_t dealias_ws_per_node(size_t elem, int N, int s, int ncls, int nrho, int nslots) {
     const size_t c = 2 * elem, N3 = size_t(N) * N * N, NI = size_t(3 * N / 2), NI3 = NI * NI * NI;
-    return c * (size_t(s) * N3 + 5 * size_t(s) * NI3 + 3 * size_t(ncls) * nrho * NI3 + size_t(nslots) * NI3 +
+    return c * (size_t(s) * N3 + 2 * size_t(s) * NI3 + size_t(ncls) * nrho * NI3 + size_t(nslots) * NI3 +
                 size_t(nslots) * N3) + 7 * 256;
 }
 // Record the error text returned by dgfs_last_error and return st (api.cpp).
