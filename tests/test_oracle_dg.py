@@ -1,11 +1,31 @@
 """Pins of the nodal DG slab oracle (Sec. 5): the GLL rule (including the K = 3 weights
 the paper prints), the Lagrange derivative, exactness of the transport operator on
 polynomials of the element degree, the discrete mass balance, the zero net flux
-through a diffuse wall, and SSP-RK2 around it."""
+through a diffuse wall, and SSP-RK2 around it; the Maxwellian that builds the inflow
+and wall states carries the density, velocity and temperature it is given."""
 import numpy as np
 import pytest
 
-from oracle import dg, spectral as S, stepping as T
+from oracle import dg, moments as Mo, spectral as S, stepping as T
+
+
+@pytest.mark.parametrize("m,n,u,T,N,L", [
+    (1.0, 1.0, (0.0, 0.0, 0.0), 1.0, 32, 6.0),
+    (2.0, 0.7, (0.3, -0.2, 0.1), 0.5, 48, 6.0),
+    (1.0, 1.3, (0.0, -0.3, 0.0), 1.7, 48, 8.0),
+    (32.75, 0.9, (0.0, 0.0, 0.05), 1.0, 48, 6.0 * np.sqrt(1.0 / 32.75)),
+])
+def test_maxwellian_moments_are_its_parameters(m, n, u, T, N, L):
+    """The nondimensional moments of Sec. 3 (n = int f, u = int v f / n,
+    T = 2m/(3n) int |v - u|^2 f), taken by the rectangle rule on a grid that resolves
+    the Maxwellian (spacing and box chosen so that the rule's error and the tails are
+    below 1e-14), return the parameters it was built with.  A wrong normalisation
+    (e.g. (m/(2 pi T))^{3/2}) or temperature convention (exp(-m v^2/(2T))) fails."""
+    f = dg.maxwellian(N, L, m, n, u, T)
+    mo = Mo.moments(f, m, L)
+    assert abs(mo["n"] - n) <= 1e-12 * n
+    np.testing.assert_allclose(mo["u"], u, rtol=0, atol=1e-12)
+    assert abs(mo["T"] - T) <= 1e-12 * T
 
 
 def test_gll_k3_is_the_printed_example():
