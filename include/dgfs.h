@@ -108,11 +108,21 @@ typedef struct {
 
 typedef struct dgfs_plan dgfs_plan;
 
+/* The pair prefactor of the dimensionless kernel, for filling dgfs_pair_kernel: Kn_ij^{-1}
+ * times the constant of the VSS kernel (Sec. 3, eqs. Kn and NVSS).  The sqrt(1 + m_i/m_j)
+ * factors of the two cancel, so
+ *     C_ij = alpha / (kn0 2^{1+alpha} Gamma(5/2 - omega) pi mu_ij^{omega - 1/2}),
+ * mu_ij = m_i m_j / (m_i + m_j), with kn0 = 1 / (pi n0 d_ref^2 (T_ref/T0)^{omega-1/2} H0)
+ * the mass-independent part of Kn_ij.  Symmetric in (m_i, m_j).  m_i, m_j, kn0 > 0,
+ * omega in [0.5, 1], alpha in [1, 2] (DGFS_EINVAL otherwise); *C receives the value.
+ * Host only: no device is touched. */
+dgfs_status dgfs_pair_prefactor(double m_i, double m_j, double omega, double alpha, double kn0, double* C);
+
 /* Host-side check of a problem description; no device is touched.
  * Returns DGFS_OK, DGFS_EINVAL or DGFS_EUNSUPPORTED. */
 dgfs_status dgfs_check_problem(const dgfs_problem* problem);
 
-/* Precompute (Sec. 4, "precompute F and G- up to a high accuracy"): quadrature,
+/* Precompute (Sec. 4, the tables F and G- computed once per problem): quadrature,
  * designs, radial kernel tables F^{ij}(|k|, rho_q), loss weights G^{ij-}(|m|) and
  * phase tables, in FP64 on the host, stored in the plan precision on the current
  * device.  *out is set only on DGFS_OK. */

@@ -18,5 +18,5 @@ from .collision import (  # noqa: F401
     pair_tables,
     vhs_kernel,
     vss_kernel,
-    vhs_prefactor,
+    pair_prefactor,
 )

@@ -16,7 +16,7 @@ DGFS_OK, DGFS_EINVAL, DGFS_EUNSUPPORTED, DGFS_ENOMEM, DGFS_EDEVICE = 0, -1, -2, 
 DGFS_FP32, DGFS_FP64 = 0, 1
 
 EXPORTED = (
-    "dgfs_check_problem", "dgfs_plan_create", "dgfs_plan_destroy", "dgfs_workspace_size",
+    "dgfs_check_problem", "dgfs_pair_prefactor", "dgfs_plan_create", "dgfs_plan_destroy", "dgfs_workspace_size",
     "dgfs_collide", "dgfs_collide_timed", "dgfs_collide_pairs", "dgfs_collide_plain", "dgfs_conserve",
     "dgfs_conserve_update", "dgfs_pair_tables", "dgfs_design", "dgfs_interpolation_matrix", "dgfs_kernel_mode",
     "dgfs_status_string", "dgfs_last_error", "dgfs_tile_candidates", "dgfs_group_create", "dgfs_group_destroy",
@@ -78,6 +78,7 @@ def load() -> ctypes.CDLL:
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1903_03056_amd.build`")
     lib = ctypes.CDLL(LIB_PATH)
     lib.dgfs_check_problem.argtypes = [POINTER(Problem)]
+    lib.dgfs_pair_prefactor.argtypes = [c_double, c_double, c_double, c_double, c_double, POINTER(c_double)]
     lib.dgfs_plan_create.argtypes = [POINTER(Problem), POINTER(c_void_p)]
     lib.dgfs_plan_destroy.argtypes = [c_void_p]
     lib.dgfs_plan_destroy.restype = None

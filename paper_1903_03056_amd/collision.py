@@ -5,7 +5,6 @@ PyTorch supplies device memory and streams; the arithmetic runs in libdgfs.so.
 from __future__ import annotations
 
 import ctypes
-import math
 from ctypes import POINTER, c_double, c_size_t, c_void_p
 
 import numpy as np
@@ -14,12 +13,12 @@ from . import _lib
 from ._lib import DGFS_FP32, DGFS_FP64, PairKernel, Problem, check, load
 
 
-def vhs_prefactor(mi: float, mj: float, omega: float, alpha: float = 1.0, kn0: float = 1.0) -> float:
-    """Kn_ij^{-1} times the constant of the dimensionless VSS kernel (Sec. 3, eqs. Kn
-    and NVSS).  The sqrt(1 + m_i/m_j) factors of the two cancel, leaving
-    alpha / (Kn0 2^{1+alpha} Gamma(5/2 - omega) pi mu_ij^{omega - 1/2}), mu_ij the reduced mass."""
-    mu = mi * mj / (mi + mj)
-    return alpha / (kn0 * 2.0 ** (1.0 + alpha) * math.gamma(2.5 - omega) * math.pi * mu ** (omega - 0.5))
+def pair_prefactor(mi: float, mj: float, omega: float, alpha: float = 1.0, kn0: float = 1.0) -> float:
+    """C_ij of the dimensionless kernel, computed by the library (dgfs_pair_prefactor)."""
+    C = c_double()
+    check(load().dgfs_pair_prefactor(float(mi), float(mj), float(omega), float(alpha), float(kn0), ctypes.byref(C)),
+          "dgfs_pair_prefactor")
+    return C.value
 
 
 def _precision_code(precision) -> int:
@@ -51,7 +50,7 @@ class _ProblemHolder:
 
 def vhs_kernel(masses, omega, alpha: float = 1.0, kn0: float = 1.0):
     s = len(masses)
-    return [[(omega, alpha, vhs_prefactor(masses[i], masses[j], omega, alpha, kn0)) for j in range(s)]
+    return [[(omega, alpha, pair_prefactor(masses[i], masses[j], omega, alpha, kn0)) for j in range(s)]
             for i in range(s)]
 
 
@@ -61,7 +60,7 @@ def vss_kernel(masses, omega, alpha, kn0: float = 1.0):
     s = len(masses)
     om = np.broadcast_to(np.asarray(omega, dtype=np.float64), (s, s))
     al = np.broadcast_to(np.asarray(alpha, dtype=np.float64), (s, s))
-    return [[(float(om[i, j]), float(al[i, j]), vhs_prefactor(masses[i], masses[j], om[i, j], al[i, j], kn0))
+    return [[(float(om[i, j]), float(al[i, j]), pair_prefactor(masses[i], masses[j], om[i, j], al[i, j], kn0))
              for j in range(s)] for i in range(s)]
 
 
@@ -145,8 +144,11 @@ class CollisionPlan:
         self.kernel = kernel
         self.precision = _precision_code(precision)
         if tile == "auto":
-            from .autotune import best_tile
-            tile = best_tile(self.masses, N, self.L, M, n_rho, kernel, precision)
+            if dealias:
+                tile = None   # the dealiased form runs the default geometry only
+            else:
+                from .autotune import best_tile
+                tile = best_tile(self.masses, N, self.L_species, M, n_rho, kernel, precision)
         self.tile = tuple(tile) if tile else None
         Lsp = self.L_species if len(set(self.L_species)) > 1 else None
         self.dealias = bool(dealias)
@@ -157,7 +159,7 @@ class CollisionPlan:
         check(self._lib.dgfs_plan_create(ctypes.byref(self._holder.problem), ctypes.byref(handle)),
               "dgfs_plan_create")
         self._plan = handle
-        self._ws = None
+        self._ws = {}
 
     @property
     def dtype(self):
@@ -168,7 +170,7 @@ class CollisionPlan:
         if getattr(self, "_plan", None):
             self._lib.dgfs_plan_destroy(self._plan)
             self._plan = None
-        self._ws = None
+        self._ws = {}
 
     def __del__(self):
         try:
@@ -181,13 +183,22 @@ class CollisionPlan:
         check(self._lib.dgfs_workspace_size(self._plan, batch, ctypes.byref(n)), "dgfs_workspace_size")
         return n.value
 
-    def workspace(self, batch: int, device=None):
-        """A cached device workspace big enough for ``batch`` nodes in one pass."""
+    def workspace(self, batch: int, device=None, stream=None):
+        """A cached device workspace big enough for ``batch`` nodes in one pass, one per
+        stream (calls on different streams may run concurrently, each needs its own).
+        It is allocated on that stream, so the caching allocator orders any reuse of its
+        memory after the work queued there."""
         import torch
+        dev = torch.device(device or "cuda")
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        key = (str(dev), st.cuda_stream)
         need = self.workspace_bytes(batch)
-        if self._ws is None or self._ws.numel() < need:
-            self._ws = torch.empty(need, dtype=torch.uint8, device=device or "cuda")
-        return self._ws
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < need:
+            with torch.cuda.stream(st):
+                ws = torch.empty(need, dtype=torch.uint8, device=dev)
+            self._ws[key] = ws
+        return ws
 
     def _check_f(self, f):
         import torch
@@ -210,10 +221,10 @@ class CollisionPlan:
             out = torch.empty(shape, dtype=f.dtype, device=f.device)
         elif tuple(out.shape) != shape or out.dtype != f.dtype or not out.is_contiguous():
             raise ValueError("out has the wrong shape, dtype or layout")
-        ws = workspace if workspace is not None else self.workspace(max(batch, 1), f.device)
+        st = stream if stream is not None else torch.cuda.current_stream(f.device)
+        ws = workspace if workspace is not None else self.workspace(max(batch, 1), f.device, st)
         if ws.data_ptr() % 256:
             raise ValueError("workspace must be 256-byte aligned")
-        st = stream if stream is not None else torch.cuda.current_stream(f.device)
         fn = self._lib.dgfs_collide_pairs if pairs else self._lib.dgfs_collide
         check(fn(self._plan, c_void_p(f.data_ptr()), c_void_p(out.data_ptr()), batch,
                  c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), c_void_p(st.cuda_stream)),
@@ -228,8 +239,8 @@ class CollisionPlan:
         batch = f.shape[0]
         if out is None:
             out = torch.empty(f.shape, dtype=f.dtype, device=f.device)
-        ws = workspace if workspace is not None else self.workspace(max(batch, 1), f.device)
         st = stream if stream is not None else torch.cuda.current_stream(f.device)
+        ws = workspace if workspace is not None else self.workspace(max(batch, 1), f.device, st)
         ms = (ctypes.c_float * 5)()
         check(self._lib.dgfs_collide_timed(self._plan, c_void_p(f.data_ptr()), c_void_p(out.data_ptr()), batch,
                                            c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
@@ -242,8 +253,8 @@ class CollisionPlan:
         self._check_f(f)
         if out is None:
             out = torch.empty(f.shape, dtype=f.dtype, device=f.device)
-        ws = workspace if workspace is not None else self.workspace(1, f.device)
         st = stream if stream is not None else torch.cuda.current_stream(f.device)
+        ws = workspace if workspace is not None else self.workspace(1, f.device, st)
         check(self._lib.dgfs_collide_plain(self._plan, c_void_p(f.data_ptr()), c_void_p(out.data_ptr()),
                                            f.shape[0], c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
                                            c_void_p(st.cuda_stream)), "dgfs_collide_plain")
@@ -272,10 +283,13 @@ class CollisionPlan:
         import torch
         self._check_f(f)
         code = {"euler": _lib.DGFS_EULER, "ssprk2": _lib.DGFS_SSPRK2}[scheme]
-        if workspace is None:
-            workspace = torch.empty(self.relax_workspace_bytes(max(f.shape[0], 1), scheme), dtype=torch.uint8,
-                                    device=f.device)
         st = stream if stream is not None else torch.cuda.current_stream(f.device)
+        if workspace is None:
+            # allocated on the stream that uses it: freed on return, its memory is reused
+            # only by work ordered after the queued steps
+            with torch.cuda.stream(st):
+                workspace = torch.empty(self.relax_workspace_bytes(max(f.shape[0], 1), scheme), dtype=torch.uint8,
+                                        device=f.device)
         check(self._lib.dgfs_relax(self._plan, c_void_p(f.data_ptr()), f.shape[0], float(dt), int(steps), code,
                                    c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
                                    c_void_p(st.cuda_stream)), "dgfs_relax")
@@ -305,7 +319,7 @@ class CollisionGroup:
         handle = c_void_p()
         check(self._lib.dgfs_group_create(arr, len(self.plans), ctypes.byref(handle)), "dgfs_group_create")
         self._group = handle
-        self._ws = None
+        self._ws = {}
 
     def close(self):
         if getattr(self, "_group", None):
@@ -324,7 +338,7 @@ class CollisionGroup:
         check(self._lib.dgfs_group_workspace_size(self._group, b, ctypes.byref(n)), "dgfs_group_workspace_size")
         return n.value
 
-    def _args(self, fs, outs, workspace):
+    def _args(self, fs, outs, workspace, st):
         import torch
         for p, f in zip(self.plans, fs):
             p._check_f(f)
@@ -334,9 +348,14 @@ class CollisionGroup:
         need = self.workspace_bytes(batches)
         ws = workspace
         if ws is None:
-            if self._ws is None or self._ws.numel() < need:
-                self._ws = torch.empty(need, dtype=torch.uint8, device=fs[0].device)
-            ws = self._ws
+            # one cached workspace per calling stream, allocated on it (the group's own
+            # streams fork from and join back to that stream)
+            key = st.cuda_stream
+            ws = self._ws.get(key)
+            if ws is None or ws.numel() < need:
+                with torch.cuda.stream(st):
+                    ws = torch.empty(need, dtype=torch.uint8, device=fs[0].device)
+                self._ws[key] = ws
         fa = (c_void_p * len(fs))(*[f.data_ptr() for f in fs])
         qa = (c_void_p * len(fs))(*[q.data_ptr() for q in outs])
         ba = (ctypes.c_int64 * len(fs))(*batches)
@@ -344,8 +363,8 @@ class CollisionGroup:
 
     def collide(self, fs, outs=None, workspace=None, stream=None):
         import torch
-        outs, ws, fa, qa, ba = self._args(fs, outs, workspace)
         st = stream if stream is not None else torch.cuda.current_stream(fs[0].device)
+        outs, ws, fa, qa, ba = self._args(fs, outs, workspace, st)
         check(self._lib.dgfs_group_collide(self._group, fa, qa, ba, c_void_p(ws.data_ptr()),
                                            ws.numel() * ws.element_size(), c_void_p(st.cuda_stream)),
               "dgfs_group_collide")
@@ -355,8 +374,8 @@ class CollisionGroup:
         """Capture collide(fs) into an executable graph; returns (graph, outs).  The
         buffers must stay alive and in place while the graph is used."""
         import torch
-        outs, ws, fa, qa, ba = self._args(fs, outs, workspace)
         st = stream if stream is not None else torch.cuda.Stream(fs[0].device)
+        outs, ws, fa, qa, ba = self._args(fs, outs, workspace, st)
         g = c_void_p()
         check(self._lib.dgfs_group_capture(self._group, fa, qa, ba, c_void_p(ws.data_ptr()),
                                            ws.numel() * ws.element_size(), c_void_p(st.cuda_stream),
@@ -435,9 +454,10 @@ class Slab:
             raise ValueError("f must be [Ne*K][s][N][N][N]")
         self.plan._check_f(f)
         code = {"euler": _lib.DGFS_EULER, "ssprk2": _lib.DGFS_SSPRK2}[scheme]
-        if workspace is None:
-            workspace = torch.empty(self.workspace_bytes(scheme), dtype=torch.uint8, device=f.device)
         st = stream if stream is not None else torch.cuda.current_stream(f.device)
+        if workspace is None:
+            with torch.cuda.stream(st):   # see CollisionPlan.relax
+                workspace = torch.empty(self.workspace_bytes(scheme), dtype=torch.uint8, device=f.device)
         check(self._lib.dgfs_slab_step(self._slab, c_void_p(f.data_ptr()), float(dt), int(steps), code,
                                        c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
                                        c_void_p(st.cuda_stream)), "dgfs_slab_step")

@@ -723,6 +723,16 @@ namespace dgfs {
 dgfs_status set_error(dgfs_status st, const std::string& msg) { return fail(st, msg); }
 }  // namespace dgfs
 
+static dgfs_status collide_impl(const dgfs_plan* plan, const void* f, void* Q, int64_t batch, void* ws,
+                                size_t ws_bytes, void* stream, bool pairs, float* stage_ms);
+
+namespace dgfs {
+dgfs_status collide_with_workspace(const dgfs_plan* plan, const void* f, void* Q, int64_t batch, void* ws,
+                                   size_t ws_bytes, void* stream) {
+    return collide_impl(plan, f, Q, batch, ws, ws_bytes, stream, false, nullptr);
+}
+}  // namespace dgfs
+
 size_t dgfs_plan::ws_per_node(bool pairs) const {
     if (!parts.empty()) {
         // per node, the largest part (its layout for one node, less its one-off slack)
@@ -751,6 +761,17 @@ size_t dgfs_plan::ws_per_node(bool pairs) const {
 extern "C" {
 
 dgfs_status dgfs_check_problem(const dgfs_problem* problem) { return check(problem); }
+
+dgfs_status dgfs_pair_prefactor(double m_i, double m_j, double omega, double alpha, double kn0, double* C) {
+    if (!C) return fail(DGFS_EINVAL, "C is required");
+    if (!(m_i > 0.0) || !(m_j > 0.0) || !std::isfinite(m_i) || !std::isfinite(m_j))
+        return fail(DGFS_EINVAL, "masses must be positive");
+    if (!(kn0 > 0.0) || !std::isfinite(kn0)) return fail(DGFS_EINVAL, "kn0 must be positive");
+    if (!(omega >= 0.5 && omega <= 1.0)) return fail(DGFS_EINVAL, "omega must be in [0.5, 1]");
+    if (!(alpha >= 1.0 && alpha <= 2.0)) return fail(DGFS_EINVAL, "alpha must be in [1, 2]");
+    *C = dgfs::pre::pair_prefactor(m_i, m_j, omega, alpha, kn0);
+    return DGFS_OK;
+}
 
 dgfs_status dgfs_design(int32_t M, double* sigma) {
     std::vector<double> pts;

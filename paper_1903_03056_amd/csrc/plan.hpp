@@ -135,6 +135,10 @@ inline size_t dealias_ws_per_node(size_t elem, int N, int s, int ncls, int nrho,
     return c * (size_t(s) * N3 + 2 * size_t(s) * NI3 + size_t(ncls) * nrho * NI3 + size_t(nslots) * NI3 +
                 size_t(nslots) * N3) + 7 * 256;
 }
+// dgfs_collide with the caller's workspace (api.cpp): the batch runs in slices of as many
+// nodes as ws_bytes holds.
+dgfs_status collide_with_workspace(const dgfs_plan* plan, const void* f, void* Q, int64_t batch, void* ws,
+                                   size_t ws_bytes, void* stream);
 // Record the error text returned by dgfs_last_error and return st (api.cpp).
 dgfs_status set_error(dgfs_status st, const std::string& msg);
 // Plain per-point FP64 path (plain.hip).

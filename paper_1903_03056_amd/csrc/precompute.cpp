@@ -138,6 +138,11 @@ double truncation_radius(double L, double mi, double mj) {
     return 2.0 * std::min(support_radius(L, mi, mj), support_radius(L, mj, mi));
 }
 
+double pair_prefactor(double mi, double mj, double omega, double alpha, double kn0) {
+    const double mu = mi * mj / (mi + mj);
+    return alpha / (kn0 * std::pow(2.0, 1.0 + alpha) * std::tgamma(2.5 - omega) * kPi * std::pow(mu, omega - 0.5));
+}
+
 double sinc(double x) {
     if (std::fabs(x) < 1e-4) {
         double x2 = x * x;

@@ -25,6 +25,12 @@ bool antipodal(const std::vector<double>& pts);
 double support_radius(double L, double mi, double mj);
 double truncation_radius(double L, double mi, double mj);
 
+// C_ij = Kn_ij^{-1} times the constant of the dimensionless VSS kernel (Sec. 3, eqs. Kn
+// and NVSS).  Kn_ij^{-1} carries sqrt(1 + m_i/m_j) and the kernel constant divides by it,
+// leaving alpha / (Kn0 2^{1+alpha} Gamma(5/2 - omega) pi mu_ij^{omega - 1/2}) with the
+// reduced mass mu_ij = m_i m_j / (m_i + m_j); symmetric in (i, j).
+double pair_prefactor(double mi, double mj, double omega, double alpha, double kn0);
+
 // sin(x)/x with the removable point.
 double sinc(double x);
 

@@ -34,6 +34,29 @@ def test_binding_names_match_header():
     assert sorted(_lib.EXPORTED) == _declared_functions()
 
 
+@pytest.mark.parametrize("mi,mj,omega,alpha,kn0", [
+    (1.0, 1.0, 0.5, 1.0, 1.0), (1.0, 2.0, 0.74, 1.0, 1.0), (1.0, 32.75, 0.5, 1.0, 0.3),
+    (66.3, 139.1, 0.81, 1.4, 0.04), (139.1 / 66.3, 1.0, 0.805, 1.36, 2.5), (4.0, 20.0, 1.0, 2.0, 1.0),
+])
+def test_pair_prefactor_matches_oracle(mi, mj, omega, alpha, kn0):
+    """C_ij of eqs. (Kn), (NVSS) computed by the library equals the oracle's, and is
+    symmetric in the two masses."""
+    from paper_1903_03056_amd import pair_prefactor
+    ref = OP.vss_prefactor(mi, mj, omega, alpha, kn0)
+    assert abs(pair_prefactor(mi, mj, omega, alpha, kn0) - ref) <= 1e-15 * ref
+    assert abs(pair_prefactor(mj, mi, omega, alpha, kn0) - ref) <= 1e-15 * ref
+
+
+def test_pair_prefactor_rejects_bad_arguments():
+    from paper_1903_03056_amd import pair_prefactor
+    from paper_1903_03056_amd._lib import DGFS_EINVAL, DgfsError
+    for args in [(0.0, 1.0, 0.74, 1.0, 1.0), (1.0, 1.0, 0.4, 1.0, 1.0), (1.0, 1.0, 0.74, 2.5, 1.0),
+                 (1.0, 1.0, 0.74, 1.0, 0.0), (1.0, float("nan"), 0.74, 1.0, 1.0)]:
+        with pytest.raises(DgfsError) as e:
+            pair_prefactor(*args)
+        assert e.value.status == DGFS_EINVAL
+
+
 def _kern(masses, omega):
     from paper_1903_03056_amd import vhs_kernel
     return vhs_kernel(masses, omega)
