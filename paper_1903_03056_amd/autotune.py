@@ -7,7 +7,9 @@ after a CZ-way split).  They trade FFT work, LDS capacity and occupancy differen
 each grid, so the tuner times every compiled candidate on the current device with a
 synthetic batch of the problem's shape and keeps the fastest.  Results are cached in
 JSON (DGFS_TUNE_CACHE, default ~/.cache/dgfs/tiles.json) keyed by device architecture,
-N, precision, M, N_rho and the species count.
+a digest of the built library, N, precision, M, N_rho, the species count, the kernel
+family (VHS or VSS) and the species' grid layout; a cached geometry the current build no
+longer compiles is tuned again.
 """
 from __future__ import annotations
 
@@ -39,14 +41,38 @@ def _store(cache):
     os.replace(tmp, path)
 
 
-def _key(N, precision, M, n_rho, s):
+_LIB_DIGEST = None
+
+
+def _lib_digest() -> str:
+    """SHA-256 (first 16 hex digits) of the loaded library file: a rebuild may change the
+    kernels' relative speed, so tuning results are kept per build."""
+    global _LIB_DIGEST
+    if _LIB_DIGEST is None:
+        import hashlib
+
+        from . import _lib
+        h = hashlib.sha256()
+        with open(_lib.LIB_PATH, "rb") as fh:
+            for block in iter(lambda: fh.read(1 << 20), b""):
+                h.update(block)
+        _LIB_DIGEST = h.hexdigest()[:16]
+    return _LIB_DIGEST
+
+
+def _key(N, precision, M, n_rho, kernel, Ls):
     import torch
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
-    return f"{arch}|N={N}|{precision}|M={M}|nrho={n_rho}|s={s}"
+    s = len(Ls)
+    family = "vss" if any(kernel[i][j][1] != 1.0 for i in range(s) for j in range(s)) else "vhs"
+    top = max(Ls)
+    grids = ",".join(f"{x / top:.6f}" for x in Ls)
+    return f"{arch}|lib={_lib_digest()}|N={N}|{precision}|M={M}|nrho={n_rho}|s={s}|{family}|grids={grids}"
 
 
 def tune(masses, N, L, M, n_rho, kernel, precision="f32", batch=32, reps=3, seed=0):
-    """Time every compiled geometry; returns {(ch, cz): median gain-kernel ms}."""
+    """Time every compiled geometry; returns {(ch, cz): median gain-kernel ms}.  L is one
+    half-width or one per species (species-specific grids)."""
     import torch
 
     from synth import inputs as I
@@ -54,13 +80,14 @@ def tune(masses, N, L, M, n_rho, kernel, precision="f32", batch=32, reps=3, seed
     from .collision import CollisionPlan, tile_candidates
 
     s = len(masses)
+    Ls = tuple(float(x) for x in np.broadcast_to(np.asarray(L, dtype=np.float64), (s,)))
     rng = np.random.default_rng(seed)
-    f = I.draw_bimaxwellian_batch(rng, batch, s, N, L, masses)
+    f = I.draw_bimaxwellian_batch(rng, batch, s, N, Ls, masses)
     dt = torch.float64 if precision in ("f64", "fp64", "float64") else torch.float32
     ft = torch.tensor(f, dtype=dt, device="cuda")
     times = {}
     for tile in tile_candidates(N, precision):
-        plan = CollisionPlan(masses, N, L, M, n_rho, kernel=kernel, precision=precision, tile=tile)
+        plan = CollisionPlan(masses, N, Ls, M, n_rho, kernel=kernel, precision=precision, tile=tile)
         out = torch.empty_like(ft)
         ws = plan.workspace(batch)
         plan.collide(ft, out=out, workspace=ws)
@@ -71,12 +98,18 @@ def tune(masses, N, L, M, n_rho, kernel, precision="f32", batch=32, reps=3, seed
 
 
 def best_tile(masses, N, L, M, n_rho, kernel, precision="f32", batch=32, reps=3):
-    """The fastest geometry for this problem shape (cached)."""
+    """The fastest geometry for this problem shape (cached).  L: one half-width or one
+    per species."""
+    from .collision import tile_candidates
+
+    s = len(masses)
+    Ls = tuple(float(x) for x in np.broadcast_to(np.asarray(L, dtype=np.float64), (s,)))
     cache = _load()
-    key = _key(N, precision, M, n_rho, len(masses))
-    if key in cache:
+    key = _key(N, precision, M, n_rho, kernel, Ls)
+    compiled = [tuple(t) for t in tile_candidates(N, precision)]
+    if key in cache and tuple(cache[key]["tile"]) in compiled:
         return tuple(cache[key]["tile"])
-    times = tune(masses, N, L, M, n_rho, kernel, precision, batch, reps)
+    times = tune(masses, N, Ls, M, n_rho, kernel, precision, batch, reps)
     best = min(times, key=times.get)
     cache[key] = {"tile": list(best), "gain_ms": {f"{k[0]}x{k[1]}": v for k, v in times.items()},
                   "batch": batch}
