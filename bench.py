@@ -166,12 +166,31 @@ def group_leg(torch, dev, replays):
     ms = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
     evals = sum(B * s * s for _, B in cfg["groups"])
     flops = sum(B * gain_flops_per_node(N, M, N // 2, s) for N, B in cfg["groups"])
+    # the same classes run one after another on one stream, each as its own collide call
+    # (no overlap between classes): the sum the graph's concurrent classes compete with
+    st = torch.cuda.current_stream(dev)
+    for p, x, q in zip(plans, fs, outs):
+        p.collide(x, out=q, workspace=p.workspace(x.shape[0], dev))
+    torch.cuda.synchronize()
+    iso = np.zeros((replays, len(plans)))
+    for k in range(replays):
+        for c, (p, x, q) in enumerate(zip(plans, fs, outs)):
+            a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a0.record(st)
+            p.collide(x, out=q, workspace=p.workspace(x.shape[0], dev))
+            a1.record(st)
+            a1.synchronize()
+            iso[k, c] = a0.elapsed_time(a1)
+    iso_ms = iso.mean(axis=0)
     res = {"workload": "uneven batch: 512 nodes N=24 + 256 N=32 + 64 N=48, 3 species m=(1,2,4), VHS "
                        "omega=0.74, L=6, M=12, N_rho=N/2, bi-Maxwellians, seed 4; one hipGraph replay per call",
            "value": round(evals / (ms.mean() * 1e-3), 1), "unit": "evals/s", "replays": replays,
            "ms_per_call": {"mean": round(float(ms.mean()), 3), "p50": round(float(np.percentile(ms, 50)), 3),
                            "p99": round(float(np.percentile(ms, 99)), 3)},
            "gain_tflops_over_call": round(flops / (ms.mean() * 1e-3) / 1e12, 2),
+           "isolated_classes_ms": {str(N): round(float(t), 3) for (N, _), t in zip(cfg["groups"], iso_ms)},
+           "isolated_sum_ms": round(float(iso_ms.sum()), 3),
+           "graph_speedup_over_isolated_sum": round(float(iso_ms.sum() / ms.mean()), 4),
            "tiles": {str(p.N): list(p.tile) if p.tile else None for p in plans},
            "setup_s_incl_autotune": round(setup_s, 1)}
     # node 0 of the N=24 and N=32 classes, for the oracle comparison of the CPU leg
@@ -181,6 +200,39 @@ def group_leg(torch, dev, replays):
     graph.close()
     group.close()
     return res, checks
+
+
+def serving_leg(torch, dev, requests=500, rate=2000.0, relaxed_s=4.0):
+    """The serving loop (continuous batching): Poisson arrivals at `rate` of spatially
+    homogeneous relaxation problems (2-3 species with masses from {1, 2, 4, 20}, N from
+    {16, 24, 32, 48}, 50 forward-Euler steps of dt = 0.01 with the FP64 projection, L = 6,
+    M = 12, N_rho = N/2), then a second trace at 0.7x the throughput the first one
+    measured, so latency without queueing is visible.  Latency = arrival -> completion."""
+    from paper_1903_03056_amd import serve as S
+    t0 = time.perf_counter()
+    backend = S.DeviceBackend()
+    trace = S.make_trace(requests, rate, 5, 50)
+    srv = S.Server(backend=backend)
+    staged, setup = srv.warm(trace)
+    over = srv.run(trace, staged)
+    rate2 = 0.7 * over["throughput_req_s"]
+    trace2 = S.make_trace(max(20, int(round(rate2 * relaxed_s))), rate2, 6, 50)
+    srv2 = S.Server(backend=backend)
+    staged2, _ = srv2.warm(trace2)
+    relaxed = srv2.run(trace2, staged2)
+    keep = ("requests", "makespan_s", "throughput_req_s", "pair_evals_per_s", "latency_p50_s", "latency_p99_s",
+            "latency_max_s", "pools", "launches", "budget_peak_bytes", "deferrals")
+
+    def pick(r, arrival):
+        out = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items() if k in keep}
+        out["arrival_rate_req_s"] = round(arrival, 2)
+        return out
+
+    return {"workload": "serving: Poisson arrivals, 2-3 species with masses from {1,2,4,20}, N from {16,24,32,48}, "
+                        "L=6, M=12, N_rho=N/2, VHS omega=0.74, 50 forward-Euler steps dt=0.01 with the FP64 "
+                        "projection per request; continuous batching in per-(N, masses) pools, HBM-budget admission",
+            "overload": pick(over, rate), "relaxed_0p7_capacity": pick(relaxed, rate2),
+            "plans_and_staging_s": round(setup, 2), "leg_s": round(time.perf_counter() - t0, 1)}
 
 
 def species_grid_leg(torch, dev, calls):
@@ -429,7 +481,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="leave out the uneven-batch, species-grid, SSP-RK2 and measured-ceiling legs")
     ap.add_argument("--only-leg", choices=["vss_slab", "dg_slab", "dealiased_slab", "uneven_group_graph",
-                                           "heavy_light_species_grids"], default=None,
+                                           "heavy_light_species_grids", "serving"], default=None,
                     help="run only the named extra workload and print its JSON (for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain device copy of 2 x 256 MiB first (calibrates HBM byte counters)")
@@ -452,6 +504,10 @@ def main():
     if args.only_leg == "uneven_group_graph":
         log("uneven batch only")
         print(json.dumps({args.only_leg: group_leg(torch, torch.device("cuda:0"), args.steps)[0]}), flush=True)
+        return
+    if args.only_leg == "serving":
+        log("serving loop only")
+        print(json.dumps({"serving": serving_leg(torch, torch.device("cuda:0"))}), flush=True)
         return
     if args.only_leg == "heavy_light_species_grids":
         log("heavy/light species grids only")
@@ -600,6 +656,8 @@ def main():
         log("SSP-RK2 stepping")
         extra["ssprk2_relax"], c = relax_leg(torch, dev, plan, f32, w, 10)
         checks += c
+        log("serving loop")
+        extra["serving"] = serving_leg(torch, dev)
         out["workloads"] = extra
     else:
         checks = []

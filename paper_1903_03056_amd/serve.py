@@ -84,8 +84,7 @@ def make_trace(n_requests=2000, rate=2000.0, seed=5, steps=50, dt=0.01, Ns=N_CHO
 def initial_state(req: Request) -> np.ndarray:
     """Seeded two-Maxwellian initial data of one request, [s][N][N][N] float32."""
     from synth import inputs as I
-    rng = np.random.default_rng([req.seed, req.rid])
-    return I.draw_bimaxwellian_batch(rng, 1, len(req.masses), req.N, L_BOX, req.masses)[0].astype(np.float32)
+    return I.draw_request_state(req.seed, req.rid, req.masses, req.N, L_BOX).astype(np.float32)
 
 
 def state_bytes(N: int, s: int) -> int:
@@ -161,6 +160,7 @@ class DevicePool:
         self.event = None
         self.f = self.Q = self.ws = None
         self.cap = 0
+        self.peak_cap = 0          # largest slot capacity the pool has held
         self._staged = []          # pinned host buffers whose copies are in flight
 
     def _ws_bytes(self, cap: int) -> int:
@@ -190,6 +190,7 @@ class DevicePool:
             self.Q = torch.empty(shape, dtype=torch.float32, device="cuda")
             self.ws = torch.empty(self._ws_bytes(cap), dtype=torch.uint8, device="cuda")
         self.cap = cap
+        self.peak_cap = max(self.peak_cap, cap)
 
     def insert(self, slot: int, staged) -> None:
         with self.torch.cuda.stream(self.stream):

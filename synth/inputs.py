@@ -23,6 +23,8 @@ __all__ = [
     "config",
     "draw_bimaxwellian_batch",
     "draw_config3_batch",
+    "draw_uneven_groups",
+    "draw_request_state",
 ]
 
 
@@ -112,3 +114,18 @@ def draw_config3_batch(rng: np.random.Generator, batch: int, N: int, L, masses) 
         f[b, 0] = maxwellian(N, Ls[0], masses[0], n1, (0.0, 0.0, 0.0), 1.0)
         f[b, 1] = maxwellian(N, Ls[1], masses[1], n2, (0.0, 0.0, 0.0), r)
     return f
+
+
+def draw_uneven_groups(seed: int, groups, s: int, L: float, masses) -> list:
+    """The uneven-N workload: one generator seeded with ``seed`` draws the classes in
+    the order given, ``groups`` = ((N, batch), ...), each by
+    ``draw_bimaxwellian_batch`` (float64 arrays [batch][s][N][N][N])."""
+    rng = np.random.default_rng(seed)
+    return [draw_bimaxwellian_batch(rng, B, s, N, L, masses) for N, B in groups]
+
+
+def draw_request_state(seed: int, rid: int, masses, N: int, L: float) -> np.ndarray:
+    """Initial two-Maxwellian state of one serving request, [s][N][N][N] float64, from a
+    generator seeded with the pair (seed, request id)."""
+    rng = np.random.default_rng([seed, rid])
+    return draw_bimaxwellian_batch(rng, 1, len(masses), N, L, masses)[0]
