@@ -150,6 +150,21 @@ dgfs_status dgfs_collide(const dgfs_plan* plan, const void* f, void* Q, int64_t 
 dgfs_status dgfs_collide_timed(const dgfs_plan* plan, const void* f, void* Q, int64_t batch,
                                void* workspace, size_t ws_bytes, void* stream, float* stage_ms);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops that must not call hipMalloc, harnesses that forbid it): dgfs_collide with a
+ * workspace owned by the library instead of the caller's.  The workspace is a static
+ * device array of dgfs_static_workspace_bytes() bytes (256 MiB) on every device the
+ * library runs on, held until the process ends; its address is looked up once per device
+ * on the first call.  The call allocates nothing; the batch runs in slices of as many
+ * nodes as that workspace holds, with results equal bit for bit to dgfs_collide's.
+ * f, Q: device arrays [batch][s][N^3] of the plan precision, as for dgfs_collide.  The
+ * plan's device must be the current device (DGFS_EINVAL otherwise); a plan whose single
+ * node needs more workspace than the array holds gives DGFS_ENOMEM.  Every call on one
+ * device shares that device's array: calls that overlap on one device (other streams,
+ * other host threads) race and give wrong results; serialise them. */
+dgfs_status dgfs_collide_static(const dgfs_plan* plan, const void* f, void* Q, int64_t batch, void* stream);
+size_t dgfs_static_workspace_bytes(void);
+
 /* Per ordered pair: Q[b][i][j] = Q^{ij}(f[b][i], f[b][j]), Q shaped [batch][s][s][N^3]. */
 dgfs_status dgfs_collide_pairs(const dgfs_plan* plan, const void* f, void* Q, int64_t batch,
                                void* workspace, size_t ws_bytes, void* stream);

@@ -17,7 +17,7 @@ DGFS_FP32, DGFS_FP64 = 0, 1
 
 EXPORTED = (
     "dgfs_check_problem", "dgfs_pair_prefactor", "dgfs_plan_create", "dgfs_plan_destroy", "dgfs_workspace_size",
-    "dgfs_collide", "dgfs_collide_timed", "dgfs_collide_pairs", "dgfs_collide_plain", "dgfs_conserve",
+    "dgfs_collide", "dgfs_collide_static", "dgfs_static_workspace_bytes", "dgfs_collide_timed", "dgfs_collide_pairs", "dgfs_collide_plain", "dgfs_conserve",
     "dgfs_conserve_update", "dgfs_pair_tables", "dgfs_design", "dgfs_interpolation_matrix", "dgfs_kernel_mode",
     "dgfs_status_string", "dgfs_last_error", "dgfs_tile_candidates", "dgfs_group_create", "dgfs_group_destroy",
     "dgfs_group_workspace_size", "dgfs_group_collide", "dgfs_group_capture", "dgfs_graph_launch",
@@ -87,6 +87,9 @@ def load() -> ctypes.CDLL:
         getattr(lib, name).argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_size_t, c_void_p]
     lib.dgfs_collide_timed.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_size_t, c_void_p,
                                        POINTER(ctypes.c_float)]
+    lib.dgfs_collide_static.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p]
+    lib.dgfs_static_workspace_bytes.argtypes = []
+    lib.dgfs_static_workspace_bytes.restype = c_size_t
     lib.dgfs_conserve.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p]
     lib.dgfs_conserve_update.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_int64, c_void_p]
     lib.dgfs_pair_tables.argtypes = [POINTER(Problem), c_int32, c_int32, POINTER(c_double), POINTER(c_double),
@@ -122,7 +125,7 @@ def load() -> ctypes.CDLL:
     lib.dgfs_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         if name not in ("dgfs_plan_destroy", "dgfs_status_string", "dgfs_last_error", "dgfs_group_destroy",
-                        "dgfs_graph_destroy", "dgfs_slab_destroy"):
+                        "dgfs_graph_destroy", "dgfs_slab_destroy", "dgfs_static_workspace_bytes"):
             getattr(lib, name).restype = c_int32
     _lib = lib
     return lib

@@ -231,6 +231,22 @@ class CollisionPlan:
               "dgfs_collide_pairs" if pairs else "dgfs_collide")
         return out
 
+    def collide_static(self, f, out=None, stream=None):
+        """collide() without a caller workspace and without any allocation in the library
+        (dgfs_collide_static: the library's static device workspace, shared by every call
+        on the device, so calls must not overlap).  ``out`` must be given where the caller
+        cannot allocate either."""
+        import torch
+        self._check_f(f)
+        if out is None:
+            out = torch.empty(f.shape, dtype=f.dtype, device=f.device)
+        elif tuple(out.shape) != tuple(f.shape) or out.dtype != f.dtype or not out.is_contiguous():
+            raise ValueError("out has the wrong shape, dtype or layout")
+        st = stream if stream is not None else torch.cuda.current_stream(f.device)
+        check(self._lib.dgfs_collide_static(self._plan, c_void_p(f.data_ptr()), c_void_p(out.data_ptr()), f.shape[0],
+                                            c_void_p(st.cuda_stream)), "dgfs_collide_static")
+        return out
+
     def collide_timed(self, f, out=None, workspace=None, stream=None):
         """dgfs_collide with per-stage HIP-event timing (synchronous).  Returns
         (Q, stage_ms) with stage_ms = [forward FFT, gain, radial+loss, inverse FFTs, combine]."""
