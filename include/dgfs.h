@@ -88,7 +88,8 @@ typedef struct {
                                         ratios; the carrying rule is this library's choice.
                                         The conservation correction then uses each species'
                                         own grid.  dgfs_collide_plain needs one common grid. */
-    int32_t N;                       /* modes per dimension: 16, 24, 32 or 48 */
+    int32_t N;                       /* modes per dimension: 16, 24, 32, 48 or 64 (64: VHS kernels
+                                        only; no slab, plain path or dealiased form) */
     int32_t M;                       /* spherical design size: 6, 12 or 24 */
     int32_t n_rho;                   /* radial Gauss-Legendre points, 1..128 */
     const dgfs_pair_kernel* kernel;  /* [s*s], row-major (i, j); must be symmetric:

@@ -26,7 +26,7 @@ constexpr double kPi = 3.14159265358979323846264338327950288;
 
 int signed_mode(int j, int N) { return j < N / 2 ? j : j - N; }
 
-bool n_supported(int N) { return N == 16 || N == 24 || N == 32 || N == 48; }
+bool n_supported(int N) { return N == 16 || N == 24 || N == 32 || N == 48 || N == 64; }
 
 dgfs_status check(const dgfs_problem* p) {
     if (!p) return fail(DGFS_EINVAL, "problem is NULL");
@@ -56,7 +56,10 @@ dgfs_status check(const dgfs_problem* p) {
             if (k.omega != t.omega || k.alpha != t.alpha || k.prefactor != t.prefactor)
                 return fail(DGFS_EINVAL, "kernel must be symmetric in (i, j)");
         }
-    if (!n_supported(p->N)) return fail(DGFS_EUNSUPPORTED, "N must be 16, 24, 32 or 48");
+    if (!n_supported(p->N)) return fail(DGFS_EUNSUPPORTED, "N must be 16, 24, 32, 48 or 64");
+    if (p->N == 64)
+        for (int i = 0; i < p->s * p->s; ++i)
+            if (p->kernel[i].alpha != 1.0) return fail(DGFS_EUNSUPPORTED, "VSS kernels need N <= 48");
     if (p->dealias != 0 && p->dealias != 1) return fail(DGFS_EINVAL, "dealias must be 0 or 1");
     if (p->dealias) {
         if (p->N != 16 && p->N != 32) return fail(DGFS_EUNSUPPORTED, "the dealiased form needs N = 16 or 32");
@@ -932,6 +935,7 @@ dgfs_status dgfs_collide_plain(const dgfs_plan* plan, const double* f, double* Q
     if (!plan->parts.empty()) return fail(DGFS_EUNSUPPORTED, "the plain path has one common grid");
     if (plan->vss) return fail(DGFS_EUNSUPPORTED, "the plain path covers the VHS family (alpha = 1)");
     if (plan->inner) return fail(DGFS_EUNSUPPORTED, "the plain path evaluates the circular form");
+    if (plan->N > 48) return fail(DGFS_EUNSUPPORTED, "the plain path is compiled for N <= 48");
     if (batch < 0) return fail(DGFS_EINVAL, "batch must be >= 0");
     if (batch == 0) return DGFS_OK;
     if (!f || !Q || !workspace) return fail(DGFS_EINVAL, "f, Q and workspace are required");

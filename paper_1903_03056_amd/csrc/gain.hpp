@@ -950,23 +950,29 @@ __global__ __launch_bounds__(256) void radial_kernel(RadialArgs<T> a) {
             }
         }
     }
+    // the chunk twiddles e^{-2 pi i kxp c / N} of this thread's k_xp, loaded once
+    cx<T> twc[CH];
+#pragma unroll
+    for (int c = 1; c < CH; ++c) twc[c] = a.tw[kxp * CH + c];
     for (int gi = 0; gi < (VSS ? 0 : ng); ++gi) {
         const int cl = a.gterms[2 * (g0 + gi)], ft = a.gterms[2 * (g0 + gi) + 1];
         const cx<T>* Pb = a.P + (int64_t(b) * a.ncls + cl) * a.nrho * (CH * PCH) + e;
         const T* Ft = a.F + int64_t(ft) * a.nrho * a.K2;
         for (int q = 0; q < a.nrho; ++q) {
-            cx<T> pc[CH];
+            // the last radix-CH step of the x-transform (decimation in time): with
+            // k_x = k_xp + j N/CH, DFT(S)(k_x) = sum_c (e^{-2 pi i kxp c / N} P_c) e^{-2 pi i j c / CH}
+            cx<T> y[CH];
 #pragma unroll
-            for (int c = 0; c < CH; ++c) pc[c] = Pb[int64_t(q) * (CH * PCH) + c * PCH];
+            for (int c = 0; c < CH; ++c) {
+                const cx<T> pc = Pb[int64_t(q) * (CH * PCH) + c * PCH];
+                y[c] = c == 0 ? pc : pc * twc[c];
+            }
+            fft<CH, -1>(y);
 #pragma unroll
             for (int j = 0; j < CH; ++j) {
-                const int kx = kxp + j * NP;
-                cx<T> Sk = pc[0];
-#pragma unroll
-                for (int c = 1; c < CH; ++c) cmac(Sk, a.tw[kx * CH + c], pc[c]);
                 const double fq = double(Ft[q * a.K2 + k2[j]]);
-                acc[j].x = fma(fq, double(Sk.x), acc[j].x);
-                acc[j].y = fma(fq, double(Sk.y), acc[j].y);
+                acc[j].x = fma(fq, double(y[j].x), acc[j].x);
+                acc[j].y = fma(fq, double(y[j].y), acc[j].y);
             }
         }
     }
@@ -1074,13 +1080,15 @@ __global__ __launch_bounds__(256) void radial_vss_kernel(RadialArgs<T> a) {
                 }
             if (nyq_any) {
 #pragma unroll
-                for (int j = 0; j < CH; ++j)
+                for (int j = 0; j < CH; ++j) {
+                    if (!nyq[j]) continue;
 #pragma unroll
                     for (int d = 0; d < 2; ++d) {
                         const int64_t o = ((int64_t(q) * 2 + d) * 2 + 1) * NREP + int64_t(j) * NP * N * KZH;
                         a0[j][d] = F0[o];
                         a1[j][d] = F1[o];
                     }
+                }
             }
 #pragma unroll
             for (int u = 0; u < NB; ++u) {
@@ -1353,6 +1361,8 @@ hipError_t run_tiles_24(const dgfs_plan& p, const void* f, void* Q, int nb, void
 hipError_t run_tiles_32(const dgfs_plan& p, const void* f, void* Q, int nb, void* ws, bool pairs, hipStream_t st,
                         hipEvent_t* ev);
 hipError_t run_tiles_48(const dgfs_plan& p, const void* f, void* Q, int nb, void* ws, bool pairs, hipStream_t st,
+                        hipEvent_t* ev);
+hipError_t run_tiles_64(const dgfs_plan& p, const void* f, void* Q, int nb, void* ws, bool pairs, hipStream_t st,
                         hipEvent_t* ev);
 // The same for plans with a VSS kernel (vss_<N>.hip).
 hipError_t run_vss_16(const dgfs_plan& p, const void* f, void* Q, int nb, void* ws, bool pairs, hipStream_t st,

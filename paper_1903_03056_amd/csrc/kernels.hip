@@ -137,8 +137,9 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Compiled gain-kernel geometries (CH, CZ) per N and precision; the first is the default
 // (the fastest measured on MI355X for that N; autotune.py re-measures on the device).
 constexpr int kTilesF32[][3] = {{16, 1, 1}, {16, 2, 1}, {16, 1, 2}, {24, 3, 1}, {24, 3, 2}, {24, 3, 4},
-                                {32, 2, 1}, {32, 4, 1}, {32, 4, 2}, {48, 6, 2}, {48, 12, 4}, {48, 12, 2}};
-constexpr int kTilesF64[][3] = {{16, 1, 1}, {24, 3, 2}, {32, 4, 2}, {48, 12, 4}};
+                                {32, 2, 1}, {32, 4, 1}, {32, 4, 2}, {48, 6, 2}, {48, 12, 4}, {48, 12, 2},
+                                {64, 16, 4}};
+constexpr int kTilesF64[][3] = {{16, 1, 1}, {24, 3, 2}, {32, 4, 2}, {48, 12, 4}, {64, 32, 8}};
 
 }  // namespace
 
@@ -178,6 +179,7 @@ hipError_t launch_collide(const dgfs_plan& p, const void* f, void* Q, int64_t nb
         case 24: return run_tiles_24(p, f, Q, int(nb), ws, pairs, st, ev);
         case 32: return run_tiles_32(p, f, Q, int(nb), ws, pairs, st, ev);
         case 48: return run_tiles_48(p, f, Q, int(nb), ws, pairs, st, ev);
+        case 64: return run_tiles_64(p, f, Q, int(nb), ws, pairs, st, ev);
         default: return hipErrorInvalidValue;
     }
 }
@@ -206,6 +208,7 @@ hipError_t launch_conserve(const dgfs_plan& p, const void* Q, double* out, void*
             case 24: run(tin, std::integral_constant<int, 24>{}); break;
             case 32: run(tin, std::integral_constant<int, 32>{}); break;
             case 48: run(tin, std::integral_constant<int, 48>{}); break;
+            case 64: run(tin, std::integral_constant<int, 64>{}); break;
             default: run(tin, std::integral_constant<int, 0>{}); break;
         }
     };

@@ -278,6 +278,7 @@ dgfs_status dgfs_slab_create(const dgfs_plan* plan, const dgfs_slab_desc* desc, 
     if (!(desc->x1 > desc->x0) || !std::isfinite(desc->x0) || !std::isfinite(desc->x1))
         return dgfs::set_error(DGFS_EINVAL, "need x1 > x0");
     if (desc->collide != 0 && desc->collide != 1) return dgfs::set_error(DGFS_EINVAL, "collide must be 0 or 1");
+    if (plan->N > 48) return dgfs::set_error(DGFS_EUNSUPPORTED, "the slab transport is compiled for N <= 48");
     dgfs_status st = check_boundary(desc->left, plan->s);
     if (st != DGFS_OK) return st;
     if ((st = check_boundary(desc->right, plan->s)) != DGFS_OK) return st;

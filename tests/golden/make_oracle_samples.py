@@ -18,6 +18,12 @@ host, and stores for every checked node:
 Serving trajectories store the same fields for the final state of each request
 (``fsum`` of the initial state, ``qmax`` = max |f^i|, ``qp`` = f^i at the samples).
 
+``oracle_krook_wu_N64.npz``: the Krook-Wu solution (Sec. 6.1, m1 = m2 = 1, L = 12, M = 6)
+at N = 64 advanced from t = 5.5 by two SSP-RK2 steps of dt = 0.01 with N_rho = 64 (the
+settings of the paper's time-evolution figure), the projected operator of the oracle;
+the final state f and its change f - f0 are stored at 4096 seeded grid points per species
+(with the largest |f - f0| point) beside their maxima over the whole grid.
+
 ``oracle_slab_transport_min.json``: the DG slab of 64 elements x 4 GLL nodes between
 diffuse walls (N = 32, the noise-free slab inputs), advanced by transport alone with
 SSP-RK2 at dt = 2e-4; min f / max f_0 after each of 20 steps.
@@ -263,6 +269,49 @@ def slab_transport_minima(steps=20, dt=2e-4):
     print(f"wrote {path}", flush=True)
 
 
+def _pair_task(args):
+    from oracle import spectral as OS
+    f, prob, i, j = args
+    return i, j, OS.collide_pair_fast(f[i], f[j], prob.pair(i, j))
+
+
+def krook_wu_N64(jobs, steps=2, dt=0.01, t0=5.5):
+    """Two SSP-RK2 steps of the Krook-Wu data at N = 64, N_rho = 64, with the four ordered
+    pairs of every stage evaluated in parallel processes."""
+    import multiprocessing as mp
+
+    from oracle import bkw, moments as OM, spectral as OS
+    kw = bkw.KrookWu(1.0, 1.0)
+    N, L, M, nrho = 64, 12.0, 6, 64
+    kern = [[(1.0, 1.0, kw.kernel_constant(i + 1, j + 1)) for j in range(2)] for i in range(2)]
+    prob = OS.Problem(masses=kw.m, L=L, N=N, M=M, nrho=nrho, kernel=kern)
+    f0, _ = kw.on_grid(N, L, t0)
+    t_start = time.time()
+    with mp.get_context("spawn").Pool(min(jobs, 4)) as pool:
+        def rhs(f):
+            Q = np.zeros_like(f)
+            for i, j, q in pool.map(_pair_task, [(f, prob, i, j) for i in range(2) for j in range(2)]):
+                Q[i] += q
+            return OM.conserve(Q, kw.m, (L, L))
+        f = f0.copy()
+        for _ in range(steps):
+            f1 = f + dt * rhs(f)
+            f = 0.5 * f + 0.5 * (f1 + dt * rhs(f1))
+    fe, _ = kw.on_grid(N, L, t0 + steps * dt)
+    d = (f - f0).reshape(2, -1)
+    rng = np.random.default_rng([SAMPLE_SEED, 64])
+    idx = np.stack([np.concatenate([[int(np.argmax(np.abs(d[i])))], rng.integers(0, N ** 3, size=4095)])
+                    for i in range(2)])
+    fr = f.reshape(2, -1)
+    path = os.path.join(HERE, "oracle_krook_wu_N64.npz")
+    meta = dict(ratio=1.0, N=N, L=L, M=M, nrho=nrho, dt=dt, steps=steps, t0=t0, scheme="ssprk2")
+    np.savez_compressed(path, idx=idx, f=np.stack([fr[i, idx[i]] for i in range(2)]),
+                        df=np.stack([d[i, idx[i]] for i in range(2)]), fmax=np.abs(fr).max(axis=1),
+                        dfmax=np.abs(d).max(axis=1), meta=np.array(json.dumps(meta)))
+    print(f"wrote {path} ({time.time() - t_start:.0f} s); error vs the exact solution "
+          f"{np.abs(f - fe).max():.3e}", flush=True)
+
+
 def _task(args):
     name, b = args
     w = workloads()[name]
@@ -298,6 +347,8 @@ def main():
     args = ap.parse_args()
     if args.only is None or "slab_transport_min" in args.only:
         slab_transport_minima()
+    if args.only is None or "krook_wu_N64" in args.only:
+        krook_wu_N64(args.jobs)
     ws = workloads()
     names = [n for n in ws if args.only is None or n in args.only]
     tasks = []

@@ -138,7 +138,7 @@ def test_host_tables_match_oracle(masses, omega, L, N, nrho):
 def test_tile_candidates_and_validation():
     from paper_1903_03056_amd import check_problem, tile_candidates
     from paper_1903_03056_amd._lib import DGFS_EUNSUPPORTED, DGFS_OK
-    for N in (16, 24, 32, 48):
+    for N in (16, 24, 32, 48, 64):
         c32 = tile_candidates(N, "f32")
         c64 = tile_candidates(N, "f64")
         assert len(c32) >= 1 and len(c64) >= 1
@@ -149,6 +149,12 @@ def test_tile_candidates_and_validation():
     for tile in tile_candidates(32, "f32"):
         assert check_problem(m, 6.0, 32, 12, 16, k, tile=tile) == DGFS_OK
     assert check_problem(m, 6.0, 32, 12, 16, k, tile=(3, 1)) == DGFS_EUNSUPPORTED
+    # N = 64: VHS kernels on one or several grids; no VSS kernels, no dealiased form
+    from paper_1903_03056_amd import vss_kernel
+    assert check_problem(m, 12.0, 64, 6, 32, k) == DGFS_OK
+    assert check_problem(m, 12.0, 64, 6, 32, k, precision="f64") == DGFS_OK
+    assert check_problem(m, 12.0, 64, 6, 32, vss_kernel(m, 0.8, 1.4)) == DGFS_EUNSUPPORTED
+    assert check_problem(m, 12.0, 64, 6, 32, k, dealias=True) == DGFS_EUNSUPPORTED
 
 
 @pytest.mark.parametrize("N,L_from,L_to", [(8, 1.0, 2.3), (16, 1.0484, 6.0), (24, 6.0, 1.0484), (48, 2.0, 2.0)])
