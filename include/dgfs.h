@@ -103,7 +103,7 @@ typedef struct {
     int32_t dealias;                 /* 0: eq. (sum) as the circular convolution the FFT
                                         evaluation computes on the N^3 grid; 1: l + m = k
                                         taken literally (no wrap-around), evaluated with
-                                        spectra zero-padded to 3N/2.  1 needs N = 16 or 32,
+                                        spectra zero-padded to 3N/2.  1 needs N = 16, 24, 32 or 48,
                                         alpha = 1, one common grid and the default tile. */
 } dgfs_problem;
 

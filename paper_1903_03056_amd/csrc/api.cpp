@@ -62,7 +62,8 @@ dgfs_status check(const dgfs_problem* p) {
             if (p->kernel[i].alpha != 1.0) return fail(DGFS_EUNSUPPORTED, "VSS kernels need N <= 48");
     if (p->dealias != 0 && p->dealias != 1) return fail(DGFS_EINVAL, "dealias must be 0 or 1");
     if (p->dealias) {
-        if (p->N != 16 && p->N != 32) return fail(DGFS_EUNSUPPORTED, "the dealiased form needs N = 16 or 32");
+        if (p->N != 16 && p->N != 24 && p->N != 32 && p->N != 48)
+            return fail(DGFS_EUNSUPPORTED, "the dealiased form needs N = 16, 24, 32 or 48");
         for (int i = 0; i < p->s * p->s; ++i)
             if (p->kernel[i].alpha != 1.0) return fail(DGFS_EUNSUPPORTED, "the dealiased form needs alpha = 1");
         if (p->L_species)

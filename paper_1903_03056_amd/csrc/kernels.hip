@@ -136,10 +136,12 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Compiled gain-kernel geometries (CH, CZ) per N and precision; the first is the default
 // (the fastest measured on MI355X for that N; autotune.py re-measures on the device).
+// N = 36 and 72 are the padded grids of the dealiased form at N = 24 and 48 only.
 constexpr int kTilesF32[][3] = {{16, 1, 1}, {16, 2, 1}, {16, 1, 2}, {24, 3, 1}, {24, 3, 2}, {24, 3, 4},
                                 {32, 2, 1}, {32, 4, 1}, {32, 4, 2}, {48, 6, 2}, {48, 12, 4}, {48, 12, 2},
-                                {64, 16, 4}};
-constexpr int kTilesF64[][3] = {{16, 1, 1}, {24, 3, 2}, {32, 4, 2}, {48, 12, 4}, {64, 32, 8}};
+                                {64, 16, 4}, {36, 3, 2}, {72, 24, 4}};
+constexpr int kTilesF64[][3] = {{16, 1, 1}, {24, 3, 2}, {32, 4, 2}, {48, 12, 4}, {64, 32, 8}, {36, 6, 4},
+                                {72, 72, 8}};
 
 }  // namespace
 
@@ -161,7 +163,9 @@ hipError_t launch_collide(const dgfs_plan& p, const void* f, void* Q, int64_t nb
     if (p.inner) {
         switch (p.N) {
             case 16: return run_dealias_16(p, *p.inner, f, Q, int(nb), ws, pairs, st, ev);
+            case 24: return run_dealias_24(p, *p.inner, f, Q, int(nb), ws, pairs, st, ev);
             case 32: return run_dealias_32(p, *p.inner, f, Q, int(nb), ws, pairs, st, ev);
+            case 48: return run_dealias_48(p, *p.inner, f, Q, int(nb), ws, pairs, st, ev);
             default: return hipErrorInvalidValue;
         }
     }

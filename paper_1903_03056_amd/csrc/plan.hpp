@@ -111,10 +111,15 @@ namespace dgfs {
 // ev: NULL, or 6 events recorded at the stage boundaries of the slice.
 hipError_t launch_collide(const dgfs_plan& p, const void* f, void* Q, int64_t nb, void* ws,
                           bool pairs, hipStream_t stream, hipEvent_t* ev);
-// The dealiased pipeline (vss_24.hip: N = 16, vss_48.hip: N = 32).
+// The dealiased pipeline (vss_24.hip: N = 16, dealias_36.hip: N = 24, vss_48.hip: N = 32,
+// dealias_72.hip: N = 48).
 hipError_t run_dealias_16(const dgfs_plan& outer, const dgfs_plan& inner, const void* f, void* Q, int nb, void* ws,
                           bool pairs, hipStream_t st, hipEvent_t* ev);
+hipError_t run_dealias_24(const dgfs_plan& outer, const dgfs_plan& inner, const void* f, void* Q, int nb, void* ws,
+                          bool pairs, hipStream_t st, hipEvent_t* ev);
 hipError_t run_dealias_32(const dgfs_plan& outer, const dgfs_plan& inner, const void* f, void* Q, int nb, void* ws,
+                          bool pairs, hipStream_t st, hipEvent_t* ev);
+hipError_t run_dealias_48(const dgfs_plan& outer, const dgfs_plan& inner, const void* f, void* Q, int nb, void* ws,
                           bool pairs, hipStream_t st, hipEvent_t* ev);
 // out != NULL: out = projection of Q (FP64); fstate != NULL: fstate += dt * projection.
 hipError_t launch_conserve(const dgfs_plan& p, const void* Q, double* out, void* fstate, double dt, int64_t nb,

@@ -235,7 +235,9 @@ def test_check_problem_dealias():
     k = _kern(m, 0.74)
     assert check_problem(m, 6.0, 16, 6, 8, k, dealias=True) == DGFS_OK
     assert check_problem(m, 6.0, 32, 12, 16, k, dealias=True) == DGFS_OK
-    assert check_problem(m, 6.0, 24, 12, 12, k, dealias=True) == DGFS_EUNSUPPORTED    # 36 not compiled
+    assert check_problem(m, 6.0, 24, 12, 12, k, dealias=True) == DGFS_OK
+    assert check_problem(m, 6.0, 48, 12, 12, k, dealias=True) == DGFS_OK
+    assert check_problem(m, 6.0, 64, 12, 12, k, dealias=True) == DGFS_EUNSUPPORTED    # 96 not compiled
     vss = [[(0.74, 1.4, 1.0)] * 2 for _ in range(2)]
     assert check_problem(m, 6.0, 16, 6, 8, vss, dealias=True) == DGFS_EUNSUPPORTED
     assert check_problem(m, 6.0, 16, 6, 8, k, L_species=(6.0, 3.0), dealias=True) == DGFS_EUNSUPPORTED

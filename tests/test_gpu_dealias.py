@@ -1,5 +1,6 @@
 """GPU parity of the dealiased form of eq. (sum) (l + m = k without wrap-around, spectra
-zero-padded to 3N/2 on the device) against the oracle's linear-convolution reading:
+zero-padded to 3N/2 on the device: 24, 36, 48, 72 for N = 16, 24, 32, 48) against the
+oracle's linear-convolution reading:
 FP64 within 1e-12, FP32 within 1e-5 relative L-inf per (node, species)."""
 import numpy as np
 import pytest
@@ -75,6 +76,29 @@ def test_dealiased_fp32_full_size_sampled():
         assert np.all(OM.conservation_residual(Qc[b], masses, (L, L)) <= 1e-12)
 
 
+@pytest.mark.parametrize("N", [24, 48])
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_dealiased_N24_N48(N, precision, tol):
+    """The padded grids of length 36 and 72 (radix 3 twice): one noisy node, M = 6,
+    N_rho = 4, summed and pair-resolved against the oracle's linear convolution (which pads
+    to 2N)."""
+    _require_gpu()
+    print(f"[case] dealiased {precision} N={N}", flush=True)
+    masses, L, M, nrho = (1.0, 2.0), 6.0, 6, 4
+    plan = _plan(masses, N, L, M, nrho, precision)
+    f = I.draw_bimaxwellian_batch(np.random.default_rng(70 + N), 1, 2, N, (L, L), masses, noise=1e-2)
+    if precision == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    ft = torch.tensor(f, dtype=plan.dtype, device="cuda")
+    Q = plan.collide(ft).double().cpu().numpy()
+    Qp = plan.collide(ft, pairs=True).double().cpu().numpy()
+    prob = OS.vhs_problem(masses, 0.74, L, N, M, nrho)
+    refp = OS.collide_pairs(f[0], prob, method="dealiased")
+    rs, rp = _rel(Q[0], refp.sum(axis=1)), _rel(Qp[0], refp)
+    print(f"summed {rs:.3e}, pairs {rp:.3e}", flush=True)
+    assert rs <= tol and rp <= tol
+
+
 def test_dealiased_rejections():
     _require_gpu()
     from paper_1903_03056_amd._lib import DgfsError
@@ -82,4 +106,4 @@ def test_dealiased_rejections():
     with pytest.raises(DgfsError):
         plan.collide_plain(torch.zeros((1, 2, 16, 16, 16), dtype=torch.float64, device="cuda"))
     with pytest.raises(DgfsError):
-        _plan((1.0, 2.0), 24, 5.0, 6, 4, "f64")
+        _plan((1.0, 2.0), 64, 5.0, 6, 4, "f64")
