@@ -31,8 +31,10 @@ enum { GAIN_REAL = 0, GAIN_COMPLEX = 1, GAIN_VSS = 2 };
 // Geometry of one work item: the x-chunk c (x-indices = c mod CH, NP = N/CH of them)
 // of one S_q field.  Each y/z pencil of the chunk is shared by CZ thread groups: group
 // cz keeps the outputs with index = cz mod CZ (decimation in frequency), so a thread
-// holds NS = N/CZ values per field.  The group index is uniform per wavefront
-// (NTC = NP*N is a multiple of 64), so every twiddle is a compile-time constant.
+// holds NS = N/CZ values per field.  The group index is uniform per wavefront when
+// NTC = NP*N is a multiple of 64, so every twiddle is a compile-time constant; the padded
+// grids of the dealiased form (36, 72) have no such split, and there the one wavefront
+// that straddles two groups runs both groups' code under its lane masks.
 template <typename T, int N, int CH, int CZ>
 struct GainK {
     static constexpr int NP = N / CH;
@@ -52,7 +54,7 @@ struct GainK {
     static constexpr int ROWC = N + 2 * NP + 1;
     static constexpr int GC = (N % 4 == 0 && 256 <= NT) ? 4 : (N % 3 == 0 && 192 <= NT) ? 3 : (128 <= NT) ? 2 : 1;
     static_assert(NP * CH == N && NS * CZ == N, "CH and CZ must divide N");
-    static_assert(NTC % 64 == 0, "a CZ group must be whole wavefronts");
+    static_assert(NTC % 64 == 0 || N % 9 == 0, "a CZ group must be whole wavefronts (except the 36, 72 grids)");
 };
 
 template <typename T>
@@ -773,16 +775,16 @@ __global__ __launch_bounds__((GainK<T, N, CH, CZ>::NT)) void gain_kernel(GainArg
 //   sum_d F_H,d U_d + i F_A,d V_d,  U_0 = (Z(k) + conj Z(-k))/2, U_1 = (Z(k) - conj Z(-k))/(2i),
 // F_H, F_A the Hermitian and anti-Hermitian parts of F (F_A vanishes off the Nyquist
 // planes, where V_d is needed).
-template <typename T>
-__device__ __forceinline__ void vss_accumulate(cx<double>& acc, const cx<T> h[2], const cx<T> fa[2], double u0x,
-                                               double u0y, double u1x, double u1y, bool nyq, const cx<T> v[2]) {
-    acc.x += double(h[0].x) * u0x - double(h[0].y) * u0y + double(h[1].x) * u1x - double(h[1].y) * u1y;
-    acc.y += double(h[0].x) * u0y + double(h[0].y) * u0x + double(h[1].x) * u1y + double(h[1].y) * u1x;
+template <typename T, typename A = double>
+__device__ __forceinline__ void vss_accumulate(cx<A>& acc, const cx<T> h[2], const cx<T> fa[2], A u0x,
+                                               A u0y, A u1x, A u1y, bool nyq, const cx<T> v[2]) {
+    acc.x += A(h[0].x) * u0x - A(h[0].y) * u0y + A(h[1].x) * u1x - A(h[1].y) * u1y;
+    acc.y += A(h[0].x) * u0y + A(h[0].y) * u0x + A(h[1].x) * u1y + A(h[1].y) * u1x;
     if (nyq) {
 #pragma unroll
         for (int d = 0; d < 2; ++d) {  // i F_A V
-            acc.x -= double(fa[d].x) * double(v[d].y) + double(fa[d].y) * double(v[d].x);
-            acc.y += double(fa[d].x) * double(v[d].x) - double(fa[d].y) * double(v[d].y);
+            acc.x -= A(fa[d].x) * A(v[d].y) + A(fa[d].y) * A(v[d].x);
+            acc.y += A(fa[d].x) * A(v[d].x) - A(fa[d].y) * A(v[d].y);
         }
     }
 }
@@ -1025,9 +1027,11 @@ __device__ __forceinline__ void mirror_paired_row(int r, int& kxp, int& ky) {
 // NB nodes' partials (read at k and -k; the second use of an unlike class finds them in
 // L2).  The per-slot
 // accumulators are indexed with compile-time slots (SMAX >= nslots) under uniform
-// compares, so they stay in registers.  Loss terms and outputs as in radial_kernel.
+// compares, so they stay in registers.  They are of the plan precision (FP32 plans sum in
+// FP32): that halves their registers and lets three waves share a SIMD, which is what
+// this latency-bound kernel needs.  Loss terms and outputs as in radial_kernel.
 template <typename T, int N, int CH, int NB, int SMAX>
-__global__ __launch_bounds__(256) void radial_vss_kernel(RadialArgs<T> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void radial_vss_kernel(RadialArgs<T> a) {
     constexpr int NP = N / CH;
     constexpr int KZH = N / 2 + 1;
     constexpr int64_t N2 = int64_t(N) * N, N3 = N2 * N, PCH = int64_t(NP) * N * KZH;
@@ -1044,13 +1048,13 @@ __global__ __launch_bounds__(256) void radial_vss_kernel(RadialArgs<T> a) {
     const int64_t eP = (int64_t(kxp) * N + ky) * N + kz, ePm = (int64_t(kxpm) * N + kym) * N + kzm;
     const int64_t fo = (int64_t(kxp) * N + ky) * KZH + kz;
 
-    cx<double> acc[NB][SMAX][CH];
+    cx<T> acc[NB][SMAX][CH];
 #pragma unroll
     for (int u = 0; u < NB; ++u)
 #pragma unroll
         for (int sl = 0; sl < SMAX; ++sl)
 #pragma unroll
-            for (int j = 0; j < CH; ++j) acc[u][sl][j] = cx<double>{0.0, 0.0};
+            for (int j = 0; j < CH; ++j) acc[u][sl][j] = cx<T>{T(0), T(0)};
 
     constexpr int N2I = N * N;
     bool nyq[CH];
@@ -1081,7 +1085,6 @@ __global__ __launch_bounds__(256) void radial_vss_kernel(RadialArgs<T> a) {
             if (nyq_any) {
 #pragma unroll
                 for (int j = 0; j < CH; ++j) {
-                    if (!nyq[j]) continue;
 #pragma unroll
                     for (int d = 0; d < 2; ++d) {
                         const int64_t o = ((int64_t(q) * 2 + d) * 2 + 1) * NREP + int64_t(j) * NP * N * KZH;
@@ -1113,12 +1116,12 @@ __global__ __launch_bounds__(256) void radial_vss_kernel(RadialArgs<T> a) {
                     }
                     cx<T> v[2];
                     if (nyq[j]) split_w<T>(Vb[vplane_index<N>(kx, ky, kz)], Vb[vplane_mirror<N>(kx, ky, kz)], v);
-                    const double u0x = 0.5 * (double(Z.x) + double(Zm.x)), u0y = 0.5 * (double(Z.y) - double(Zm.y));
-                    const double u1x = 0.5 * (double(Z.y) + double(Zm.y)), u1y = 0.5 * (double(Zm.x) - double(Z.x));
+                    const T u0x = T(0.5) * (Z.x + Zm.x), u0y = T(0.5) * (Z.y - Zm.y);
+                    const T u1x = T(0.5) * (Z.y + Zm.y), u1y = T(0.5) * (Zm.x - Z.x);
 #pragma unroll
                     for (int sl = 0; sl < SMAX; ++sl) {
-                        if (sl == s0) vss_accumulate<T>(acc[u][sl][j], h0[j], a0[j], u0x, u0y, u1x, u1y, nyq[j], v);
-                        if (sl == s1) vss_accumulate<T>(acc[u][sl][j], h1[j], a1[j], u0x, u0y, u1x, u1y, nyq[j], v);
+                        if (sl == s0) vss_accumulate<T, T>(acc[u][sl][j], h0[j], a0[j], u0x, u0y, u1x, u1y, nyq[j], v);
+                        if (sl == s1) vss_accumulate<T, T>(acc[u][sl][j], h1[j], a1[j], u0x, u0y, u1x, u1y, nyq[j], v);
                     }
                 }
             }
