@@ -109,6 +109,24 @@ def cpu_baseline(f64, max_seconds=12.0):
                       f"({dt:.1f} s)"}, outs
 
 
+def stored_oracle_errors(name, Q, summed_scale="qmax"):
+    """Sampled FP64 oracle results of the nodes stored for workload `name`
+    (tests/golden/oracle_<name>.npz, written from the oracle alone): max over the sampled
+    points of |Q - Q_ref| per (node, species), over max_v |Q_ref| or, with
+    summed_scale="loss", over the largest of the pairs' loss terms max_v |f^i nu^{ij}|.
+    Q: device tensor of the whole batch.  Returns the max and median over (node, species)."""
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_{name}.npz")
+    d = np.load(path, allow_pickle=False)
+    errs = []
+    for k, b in enumerate(d["nodes"]):
+        q = Q[int(b)].double().cpu().numpy().reshape(d["qmax"].shape[1], -1)
+        ref = d["qp"][k].sum(axis=1)
+        scale = d["qmax"][k] if summed_scale == "qmax" else d["loss"][k].max(axis=1)
+        errs += [float(np.abs(q[i, d["idx"][k][i]] - ref[i]).max() / scale[i]) for i in range(q.shape[0])]
+    return {"nodes": len(d["nodes"]), "scale": "max|Q|" if summed_scale == "qmax" else "loss term",
+            "max": max(errs), "median": float(np.median(errs))}
+
+
 def measured_peaks(torch, dev):
     """A 1 GiB device copy (HBM read + write) and the library's FMA-loop probe."""
     import ctypes
@@ -192,7 +210,9 @@ def group_leg(torch, dev, replays):
            "isolated_sum_ms": round(float(iso_ms.sum()), 3),
            "graph_speedup_over_isolated_sum": round(float(iso_ms.sum() / ms.mean()), 4),
            "tiles": {str(p.N): list(p.tile) if p.tile else None for p in plans},
-           "setup_s_incl_autotune": round(setup_s, 1)}
+           "setup_s_incl_autotune": round(setup_s, 1),
+           "rel_linf_vs_stored_oracle_samples": {str(N): stored_oracle_errors(f"uneven_N{N}", q)
+                                                 for (N, _), q in zip(cfg["groups"], outs)}}
     # node 0 of the N=24 and N=32 classes, for the oracle comparison of the CPU leg
     checks = [dict(leg="uneven_group_graph", key=str(N), f=host[k][0].astype(np.float64),
                    got=outs[k][0].double().cpu().numpy(), masses=masses, omega=omega, Ls=(L,) * s, N=N, M=M,
@@ -267,7 +287,12 @@ def species_grid_leg(torch, dev, calls):
            "ms_per_call": {"mean": round(float(ms.mean()), 2), "p50": round(float(np.percentile(ms, 50)), 2),
                            "p99": round(float(np.percentile(ms, 99)), 2)},
            "gain_tflops_over_call": round(flops / (ms.mean() * 1e-3) / 1e12, 2),
-           "tile": list(plan.tile) if plan.tile else None, "setup_s_incl_autotune": round(setup_s, 1)}
+           "tile": list(plan.tile) if plan.tile else None, "setup_s_incl_autotune": round(setup_s, 1),
+           # Maxwellians at rest: Q^i is a few per cent of its gain and loss terms, so both
+           # measures are reported
+           "rel_linf_vs_stored_oracle_samples": {"over_max_Q": stored_oracle_errors("heavy_light_N48", Q),
+                                                 "over_loss_term": stored_oracle_errors("heavy_light_N48", Q,
+                                                                                        "loss")}}
     # the last node (in the ragged final slice), for the oracle comparison of the CPU leg
     checks = [dict(leg="heavy_light_species_grids", key="last node", f=f[B - 1].astype(np.float64),
                    got=Q[B - 1].double().cpu().numpy(), masses=masses, omega=cfg["omega"], Ls=Ls, N=N, M=M,
@@ -336,7 +361,8 @@ def vss_leg(torch, dev, calls):
                           "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                           "frac": round(radial_bytes / (stage[2] * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
                           "bytes_per_launch": radial_bytes}},
-           "setup_s": round(setup_s, 2)}
+           "setup_s": round(setup_s, 2),
+           "rel_linf_vs_stored_oracle_samples": stored_oracle_errors("vss_slab_N32", Q)}
     return res
 
 
@@ -618,6 +644,7 @@ def main():
                               "unit": "GB/s", "frac": round(cons_gbps / PEAK_HBM_GBPS, 4),
                               "bytes_per_launch": cons_bytes},
         "precompute_s": round(precompute_s, 3),
+        "rel_linf_vs_stored_oracle_samples": stored_oracle_errors("slab_N32", Q),
     }
     Qh = Q.double().cpu().numpy()
     Qch = Qc[:4].cpu().numpy()
