@@ -77,7 +77,8 @@ def tune(masses, N, L, M, n_rho, kernel, precision="f32", batch=32, reps=3, seed
 
     from synth import inputs as I
 
-    from .collision import CollisionPlan, tile_candidates
+    from ._lib import DGFS_OK
+    from .collision import CollisionPlan, check_problem, tile_candidates
 
     s = len(masses)
     Ls = tuple(float(x) for x in np.broadcast_to(np.asarray(L, dtype=np.float64), (s,)))
@@ -87,6 +88,10 @@ def tune(masses, N, L, M, n_rho, kernel, precision="f32", batch=32, reps=3, seed
     ft = torch.tensor(f, dtype=dt, device="cuda")
     times = {}
     for tile in tile_candidates(N, precision):
+        # geometries the problem does not admit (the matrix-core one needs VHS kernels)
+        Lsp = Ls if len(set(Ls)) > 1 else None
+        if check_problem(masses, max(Ls), N, M, n_rho, kernel, precision, Lsp, tile=tile) != DGFS_OK:
+            continue
         plan = CollisionPlan(masses, N, Ls, M, n_rho, kernel=kernel, precision=precision, tile=tile)
         out = torch.empty_like(ft)
         ws = plan.workspace(batch)

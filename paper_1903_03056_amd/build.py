@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libdgfs.so")
 OBJ = os.path.join(ROOT, "_build")
 
 SOURCES = ["api.cpp", "precompute.cpp", "kernels.hip", "plain.hip", "resample.hip", "probe.hip", "slab.hip",
-           "static_scratch.hip",
+           "static_scratch.hip", "gain_mfma.hip",
            "tiles_16.hip", "tiles_24.hip", "tiles_32.hip", "tiles_48.hip", "tiles_64.hip",
            "vss_16.hip", "vss_24.hip", "vss_32.hip", "vss_48.hip", "dealias_36.hip", "dealias_72.hip"]
 

@@ -75,6 +75,10 @@ dgfs_status check(const dgfs_problem* p) {
     dgfs::GainGeometry g;
     if (!dgfs::gain_geometry(p->N, p->precision, &g))
         return fail(DGFS_EUNSUPPORTED, "no kernel for this N at this precision");
+    if (p->tile_ch != 0 && p->tile_cz == 0)
+        for (int i = 0; i < p->s * p->s; ++i)
+            if (p->kernel[i].alpha != 1.0)
+                return fail(DGFS_EUNSUPPORTED, "the matrix-core geometry (cz = 0) needs alpha = 1");
     if (p->tile_ch != 0 || p->tile_cz != 0) {
         dgfs::GainGeometry cand[16];
         const int n = dgfs::tile_candidates(p->N, p->precision, cand, 16);
@@ -83,6 +87,15 @@ dgfs_status check(const dgfs_problem* p) {
         if (!ok) return fail(DGFS_EUNSUPPORTED, "tile geometry not compiled for this N and precision");
     }
     return DGFS_OK;
+}
+
+// Whether the default geometry may be the matrix-core one: VHS kernels (alpha = 1) and
+// the circular form.
+bool matrix_default(const dgfs_problem* p) {
+    if (p->dealias) return false;
+    for (int i = 0; i < p->s * p->s; ++i)
+        if (p->kernel[i].alpha != 1.0) return false;
+    return true;
 }
 
 // Half-width of the box the ordered pair (i, j) is evaluated on: the common L, or with
@@ -294,6 +307,67 @@ void push_uses(dgfs::SlotSet& S, int ncls, std::vector<char>& blob) {
     push_int(blob, S.off_cuses, S.cuses);
 }
 
+// Matrix-core gain tables (geometry CZ = 0: FP32 VHS plans at N = 32).  Per (direction,
+// rho, field) the operands of the three shift contractions, every entry split into FP16
+// hi and lo, in the MFMA lane layouts the kernel reads ([x, z, y][chunk or k-step][hi,
+// lo][lane][8]), and the Nyquist coefficients s = -sin(N theta / 2) / N.  The real part of
+// the shift matrix is circulant, C(n, m) = c((n - m) mod N) with
+// c(d) = (1/N) sum_{l=-N/2}^{N/2-1} cos(l (2 pi d / N + theta)); theta as for the phases.
+void build_mfma_tables(dgfs_plan& P, std::vector<char>& blob) {
+    const int N = P.N, nrho = P.nrho;
+    constexpr size_t TABH = 3 * 2 * 2 * 64 * 8;
+    std::vector<_Float16> tab(size_t(P.total_dirs) * nrho * 2 * TABH);
+    std::vector<double> sc(size_t(P.total_dirs) * nrho * 2 * 4, 0.0);
+    auto md = [N](int x) { return ((x % N) + N) % N; };
+    for (const auto& c : P.classes) {
+        const dgfs::PairParams& pp = P.pair[c.i * P.s + c.j];
+        for (int d = 0; d < c.ndir; ++d) {
+            const double* sg = &P.sigma[3 * c.dirs[d]];
+            for (int q = 0; q < nrho; ++q)
+                for (int fld = 0; fld < 2; ++fld) {
+                    const double sgn = fld == 0 ? 1.0 : -1.0, coef = fld == 0 ? c.a : c.b;
+                    const size_t t = (size_t(c.dir_offset + d) * nrho + q) * 2 + fld;
+                    std::vector<double> cv[3];
+                    for (int ax = 0; ax < 3; ++ax) {
+                        const double th = sgn * kPi * pp.rho[q] * coef * sg[ax] / P.L;
+                        cv[ax].resize(N);
+                        for (int dd = 0; dd < N; ++dd) {
+                            double acc = 0.0;
+                            for (int l = -N / 2; l < N / 2; ++l) acc += std::cos(l * (2.0 * kPi * dd / N + th));
+                            cv[ax][dd] = acc / N;
+                        }
+                        sc[t * 4 + ax] = -std::sin(N * th / 2.0) / N;
+                    }
+                    _Float16* base = tab.data() + t * TABH;
+                    auto put = [&](int part, int sub, int lane, int e, double v) {
+                        const float fv = float(v);
+                        const _Float16 hi = _Float16(fv);
+                        base[((size_t(part) * 2 + sub) * 2 + 0) * 512 + lane * 8 + e] = hi;
+                        base[((size_t(part) * 2 + sub) * 2 + 1) * 512 + lane * 8 + e] = _Float16(fv - float(hi));
+                    };
+                    for (int lane = 0; lane < 64; ++lane)
+                        for (int e = 0; e < 8; ++e) {
+                            const int g = lane / 16, m = lane % 16, h = lane / 32, l32 = lane % 32;
+                            // x: B operand of a 16x16x32 tile, k = x' = 8g + e, n = m (x = 2m + chunk)
+                            for (int ch = 0; ch < 2; ++ch) put(0, ch, lane, e, cv[0][md(2 * m + ch - (8 * g + e))]);
+                            for (int s2 = 0; s2 < 2; ++s2) {
+                                // z: B operand of 32x32x16, k = z = 16 s + 8 h + e, n = z_out = l32
+                                put(1, s2, lane, e, cv[2][md(l32 - (16 * s2 + 8 * h + e))]);
+                                // y: A operand of 32x32x16, row y_out = l32, k-slot (s, h, e) = the
+                                // row 8(r/4) + 4h + r%4 (r = 8s + e) of the previous output
+                                const int r = 8 * s2 + e, yk = 8 * (r / 4) + 4 * h + r % 4;
+                                put(2, s2, lane, e, cv[1][md(l32 - yk)]);
+                            }
+                        }
+                }
+        }
+    }
+    P.off_mtab = (blob.size() + 255) & ~size_t(255);
+    blob.resize(P.off_mtab + tab.size() * sizeof(_Float16));
+    std::memcpy(blob.data() + P.off_mtab, tab.data(), tab.size() * sizeof(_Float16));
+    push_real<float>(blob, P.off_msc, sc);
+}
+
 template <typename T>
 void build_tables(dgfs_plan& P, std::vector<char>& blob) {
     const int N = P.N, s = P.s, nrho = P.nrho, CH = P.geo.CH, NP = N / CH;
@@ -343,6 +417,7 @@ void build_tables(dgfs_plan& P, std::vector<char>& blob) {
     }
     push_cplx<T>(blob, P.off_kx, kx);
     push_cplx<T>(blob, P.off_yz, yz);
+    if (P.geo.CZ == 0) build_mfma_tables(P, blob);
     push_real<T>(blob, P.off_nyq, nyq);
     push_int(blob, P.off_cls, cls);
     push_real<T>(blob, P.off_wdir, wdir);
@@ -497,7 +572,7 @@ dgfs_status create_single(const dgfs_problem* problem, const std::vector<unsigne
     P->mass.assign(problem->mass, problem->mass + problem->s);
     P->Ls.assign(problem->s, problem->L);
     P->mask = mask;
-    dgfs::gain_geometry(P->N, P->precision, &P->geo);
+    dgfs::gain_geometry(P->N, P->precision, &P->geo, matrix_default(problem));
     if (problem->tile_ch != 0 || problem->tile_cz != 0) P->geo = dgfs::GainGeometry{problem->tile_ch, problem->tile_cz};
     dgfs::pre::design(P->M, P->sigma);
     P->antipodal = dgfs::pre::antipodal(P->sigma);
@@ -578,7 +653,7 @@ dgfs_status create_species_grids(const dgfs_problem* problem, dgfs_plan** out) {
     P->Ls.assign(problem->L_species, problem->L_species + s);
     P->L = *std::max_element(P->Ls.begin(), P->Ls.end());
     P->mask.assign(size_t(s) * s, 1);
-    dgfs::gain_geometry(P->N, P->precision, &P->geo);
+    dgfs::gain_geometry(P->N, P->precision, &P->geo, matrix_default(problem));
     if (problem->tile_ch != 0 || problem->tile_cz != 0) P->geo = dgfs::GainGeometry{problem->tile_ch, problem->tile_cz};
     std::vector<double> boxes;
     for (int i = 0; i < s; ++i)
@@ -759,7 +834,9 @@ size_t dgfs_plan::ws_per_node(bool pairs) const {
     // f_hat, the partials, and the gain and loss spectra of every slot (their k_z <= N/2
     // halves: the spectra are Hermitian)
     const size_t half = 2 * elem() * size_t(N) * N * (N / 2 + 1);
-    return c * size_t(s) + 2 * half * size_t(nslots) + part * classes.size() * size_t(nrho);
+    // the matrix-core gain's prepared inputs (one alignment more: ws_slack)
+    const size_t prep = geo.CZ == 0 ? size_t(s) * dgfs::mfma_prep_bytes : 0;
+    return c * size_t(s) + 2 * half * size_t(nslots) + part * classes.size() * size_t(nrho) + prep;
 }
 
 extern "C" {

@@ -597,6 +597,72 @@ __device__ __forceinline__ void packed_direction(const cx<T>* __restrict__ fa, c
     __syncthreads();
 }
 
+// Forward transform of one work item's field, held in buf (LDS) as rows (plane m of the
+// chunk, y) of z values with row stride N + 1: z and y passes through LDS, then the chunk's
+// part of the x-transform; stores the chunk partial (Pq: the partials of this (node, class,
+// rho_q), chunk c at offset c * N/CH * pencils).  CPLX: the field is complex and every (k_y,
+// k_z) pencil is stored; otherwise the field is real, its partial Hermitian, and only
+// k_z <= N/2 is stored.  Needs every thread of the work item (GainK<T, N, CH, CZ>::NT).
+template <typename T, int N, int CH, int CZ, bool CPLX>
+__device__ __forceinline__ void store_partial(cx<T>* buf, cx<T>* Pq, int c) {
+    using K = GainK<T, N, CH, CZ>;
+    const int tid = threadIdx.x;
+    const int cz = tid / K::NTC, u = tid % K::NTC;
+    const int m = u / N, r = u % N;
+    {
+        cx<T> v[K::NS];
+        with_group<CZ>(cz, [&](auto gg) {
+            split_fft<N, CZ, decltype(gg)::value, -1, 1>(buf + (m * N + r) * K::ROW, v);
+        });
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < K::NS; ++j) buf[(m * N + r) * K::ROW + CZ * j + cz] = v[j];
+        __syncthreads();
+        with_group<CZ>(cz, [&](auto gg) {
+            split_fft<N, CZ, decltype(gg)::value, -1, K::ROW>(buf + (m * N) * K::ROW + r, v);
+        });
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < K::NS; ++j) buf[(m * N + CZ * j + cz) * K::ROW + r] = v[j];
+        __syncthreads();
+    }
+    if constexpr (CPLX) {
+        // the transform of a complex field: every (k_y, k_z) pencil is stored
+        constexpr int64_t PCHF = int64_t(K::NP) * K::NPENF;
+        cx<T>* Pout = Pq + int64_t(c) * PCHF;
+#pragma unroll 1
+        for (int k = 0; k < K::PXF; ++k) {
+            const int P = tid + k * K::NT;
+            if (K::PXF * K::NT != K::NPENF && P >= K::NPENF) break;
+            const int ky = P / N, kz = P % N;
+            cx<T> v[K::NP];
+#pragma unroll
+            for (int mm = 0; mm < K::NP; ++mm) v[mm] = buf[(mm * N + ky) * K::ROW + kz];
+            fft<K::NP, -1>(v);
+#pragma unroll
+            for (int kk = 0; kk < K::NP; ++kk) Pout[kk * K::NPENF + P] = v[kk];
+        }
+        return;
+    }
+    // The chunk's partial is the DFT of a real array over (x-planes of the chunk, y, z),
+    // so it is Hermitian in (k_xp, k_y, k_z): only k_z <= N/2 is stored, the radial kernel
+    // reads the rest as conjugates of the mirrored entries.
+    constexpr int64_t PCH = int64_t(K::NP) * K::NPEN;  // stored values of one chunk partial
+    cx<T>* Pout = Pq + int64_t(c) * PCH;
+#pragma unroll 1
+    for (int k = 0; k < K::PX; ++k) {
+        const int P = tid + k * K::NT;
+        if (K::PX * K::NT != K::NPEN && P >= K::NPEN) break;
+        const int ky = P / K::KZH, kz = P % K::KZH;
+        cx<T> v[K::NP];
+#pragma unroll
+        for (int mm = 0; mm < K::NP; ++mm) v[mm] = buf[(mm * N + ky) * K::ROW + kz];
+        fft<K::NP, -1>(v);
+#pragma unroll
+        for (int kk = 0; kk < K::NP; ++kk) Pout[kk * K::NPEN + P] = v[kk];
+    }
+}
+
 template <typename T, int N, int CH, int CZ, bool PIPE, bool PACK, int MODE>
 __global__ __launch_bounds__((GainK<T, N, CH, CZ>::NT)) void gain_kernel(GainArgs<T> a) {
     using K = GainK<T, N, CH, CZ>;
@@ -707,66 +773,16 @@ __global__ __launch_bounds__((GainK<T, N, CH, CZ>::NT)) void gain_kernel(GainArg
         for (int d = 0; d < ndir; ++d) direction(d, S);
     }
 
-    // forward DFT of Re S_q (complex modes: of S + i S1): z and y through LDS, then the
-    // chunk's part of x
+    // forward DFT of Re S_q (complex modes: of S + i S1): the field goes to LDS as rows
+    // (plane, y) of z values
 #pragma unroll
     for (int j = 0; j < K::NS; ++j) {
         if constexpr (CPLX) buf[(m * N + r) * K::ROW + CZ * j + cz] = cx<T>{S[j], S1[j]};
         else buf[(m * N + r) * K::ROW + CZ * j + cz] = cx<T>{S[j], T(0)};
     }
     __syncthreads();
-    {
-        cx<T> v[K::NS];
-        with_group<CZ>(cz, [&](auto gg) {
-            split_fft<N, CZ, decltype(gg)::value, -1, 1>(buf + (m * N + r) * K::ROW, v);
-        });
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < K::NS; ++j) buf[(m * N + r) * K::ROW + CZ * j + cz] = v[j];
-        __syncthreads();
-        with_group<CZ>(cz, [&](auto gg) {
-            split_fft<N, CZ, decltype(gg)::value, -1, K::ROW>(buf + (m * N) * K::ROW + r, v);
-        });
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < K::NS; ++j) buf[(m * N + CZ * j + cz) * K::ROW + r] = v[j];
-        __syncthreads();
-    }
-    if constexpr (CPLX) {
-        // the transform of a complex field: every (k_y, k_z) pencil is stored
-        constexpr int64_t PCHF = int64_t(K::NP) * K::NPENF;
-        cx<T>* Pout = a.P + ((int64_t(b) * a.ncls + cl) * a.nrho + q) * (CH * PCHF) + int64_t(c) * PCHF;
-#pragma unroll 1
-        for (int k = 0; k < K::PXF; ++k) {
-            const int P = tid + k * K::NT;
-            if (K::PXF * K::NT != K::NPENF && P >= K::NPENF) break;
-            const int ky = P / N, kz = P % N;
-            cx<T> v[K::NP];
-#pragma unroll
-            for (int mm = 0; mm < K::NP; ++mm) v[mm] = buf[(mm * N + ky) * K::ROW + kz];
-            fft<K::NP, -1>(v);
-#pragma unroll
-            for (int kk = 0; kk < K::NP; ++kk) Pout[kk * K::NPENF + P] = v[kk];
-        }
-        return;
-    }
-    // The chunk's partial is the DFT of a real array over (x-planes of the chunk, y, z),
-    // so it is Hermitian in (k_xp, k_y, k_z): only k_z <= N/2 is stored, the radial kernel
-    // reads the rest as conjugates of the mirrored entries.
-    constexpr int64_t PCH = int64_t(K::NP) * K::NPEN;  // stored values of one chunk partial
-    cx<T>* Pout = a.P + ((int64_t(b) * a.ncls + cl) * a.nrho + q) * (CH * PCH) + int64_t(c) * PCH;
-#pragma unroll 1
-    for (int k = 0; k < K::PX; ++k) {
-        const int P = tid + k * K::NT;
-        if (K::PX * K::NT != K::NPEN && P >= K::NPEN) break;
-        const int ky = P / K::KZH, kz = P % K::KZH;
-        cx<T> v[K::NP];
-#pragma unroll
-        for (int mm = 0; mm < K::NP; ++mm) v[mm] = buf[(mm * N + ky) * K::ROW + kz];
-        fft<K::NP, -1>(v);
-#pragma unroll
-        for (int kk = 0; kk < K::NP; ++kk) Pout[kk * K::NPEN + P] = v[kk];
-    }
+    cx<T>* Pq = a.P + ((int64_t(b) * a.ncls + cl) * a.nrho + q) * int64_t(CH) * K::NP * (CPLX ? K::NPENF : K::NPEN);
+    store_partial<T, N, CH, CZ, CPLX>(buf, Pq, c);
 }
 
 // =============================================================== radial kernel
@@ -1234,15 +1250,22 @@ __global__ __launch_bounds__(256) void zpass_combine_kernel(const cx<T>* __restr
     for (int z = 0; z < N; ++z) q[z] = vg[z].x - fr[z] * vl[z].x;
 }
 
+// The gain stage of FP32 VHS plans at N = 32 on the matrix cores (gain_mfma.hip, geometry
+// (2, 0)): prepares each (node, species) input in `prep` (mfma_prep_bytes per pair) and
+// writes the chunk partials P exactly as gain_kernel<float, 32, 2, 1> lays them out.
+hipError_t launch_gain_mfma32(const dgfs_plan& p, const float* f, cx<float>* P, void* prep, int nb, hipStream_t st);
+
 namespace detail {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // ev (optional): 6 events recorded at the stage boundaries (start, after forward FFT,
 // after gain, after radial, after the inverse x/y passes, after the z-pass + combine).
-template <typename T, int N, int CH, int CZ, bool PIPE, bool PACK, bool VSS>
+// MF: the gain stage runs on the matrix cores (FP32, N = 32, VHS only).
+template <typename T, int N, int CH, int CZ, bool PIPE, bool PACK, bool VSS, bool MF = false>
 hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, bool pairs, hipStream_t st,
                      hipEvent_t* ev) {
+    static_assert(!MF || (std::is_same_v<T, float> && N == 32 && CH == 2 && !VSS), "matrix-core gain: FP32 VHS N = 32");
     constexpr int MODE = VSS ? GAIN_VSS : GAIN_REAL;
     auto mark = [&](int k) {
         if (ev) hipEventRecord(ev[k], st);
@@ -1286,10 +1309,17 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
     ga.ncls = ncls;
     ga.nrho = p.nrho;
     ga.nb = nb;
-    const int64_t ipn = int64_t(ncls) * p.nrho * CH;
-    const int64_t groups = ((nb + 7) / 8) * 8 * ipn;
-    gain_kernel<T, N, CH, CZ, PIPE, PACK, MODE><<<dim3(unsigned(groups)), dim3(GainK<T, N, CH, CZ>::NT), 0, st>>>(ga);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if constexpr (MF) {
+        // the prepared inputs follow the loss spectra
+        char* prep = reinterpret_cast<char*>(Lt + int64_t(nb) * ss.nslots * NH);
+        prep += (256 - reinterpret_cast<uintptr_t>(prep) % 256) % 256;
+        if ((e = launch_gain_mfma32(p, f, P, prep, nb, st)) != hipSuccess) return e;
+    } else {
+        const int64_t ipn = int64_t(ncls) * p.nrho * CH;
+        const int64_t groups = ((nb + 7) / 8) * 8 * ipn;
+        gain_kernel<T, N, CH, CZ, PIPE, PACK, MODE><<<dim3(unsigned(groups)), dim3(GainK<T, N, CH, CZ>::NT), 0, st>>>(ga);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     if constexpr (VSS) {
         nyquist_dft_kernel<T, N, CH><<<dim3(unsigned(int64_t(nb) * ncls * p.nrho)), dim3(3 * N), 0, st>>>(PL, Vn);
         if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -1,0 +1,484 @@
+// The gain stage of Sec. 4 on the matrix cores, for FP32 plans with VHS kernels at N = 32
+// (gain geometry (2, 0)).  It produces the same chunk partials as gain_kernel<float, 32, 2,
+// 1>: for each (node, gain class, rho_q, x-chunk c) the partial forward DFT of
+// S_q = sum_p w_p Re(A_p B_p) over the x-planes x = 2m + c.
+//
+// The shifted field A = f(v + a rho sigma) is formed in physical space as a separable
+// operator, A = (R_x (x) R_y (x) R_z) f, with the N x N trigonometric-shift matrices
+//   R(n, m) = (1/N) sum_{l=-N/2}^{N/2-1} e^{i l (2 pi (n-m)/N + theta)},
+// theta = +-pi rho c sigma_d / L per axis (the same phases as the spectral form; the DFT
+// index N/2 is the mode -N/2).  R = C + i s u u^T with C = Re R (circulant), s =
+// -sin(N theta / 2) / N and u = ((-1)^n): the imaginary part is rank one.  Expanding the
+// product over the three axes:
+//   Re A = T - s_x s_y u_x u_y L_xy(z) - s_x s_z u_x u_z L_xz(y) - s_y s_z u_y u_z L_yz(x)
+//   Im A = s_x u_x P_x(y,z) + s_y u_y P_y(x,z) + s_z u_z P_z(x,y) - s_x s_y s_z u_x u_y u_z a_xyz
+// with T = C_x C_y C_z f, P_x = C_y C_z a_x, P_y = C_x C_z a_y, P_z = C_x C_y a_z,
+// L_xy = C_z a_xy, L_xz = C_y a_xz, L_yz = C_x a_yz, where a_E is f summed with the signs
+// (-1)^n over the axes in E.  T is three dense contractions (the MFMAs); the other terms
+// are planes, lines and a scalar.
+//
+// Arithmetic: every MFMA operand is split as hi + lo in FP16 (hi = f16(v), lo = f16(v -
+// hi)) and a product is hi*hi + hi*lo + lo*hi, accumulated in FP32 (about 2^-22 of each
+// operand).  The input of each (node, species) is scaled by a power of two so that its
+// largest value lies in [2^7, 2^8), which keeps every split operand in FP16's normal range
+// (planes of alternating sums reach 2^13 times the shift matrices' row sums); the scale is
+// undone in the class weight.
+//
+// Work item layout (512 threads = 8 wavefronts): wavefront w owns the x-planes m = 2w,
+// 2w + 1 of the chunk; after the last contraction lane l of a wavefront holds, per plane,
+// the rows y = 8(r/4) + 4(l/32) + r%4 (r < 16) at z = l%32 (the MFMA 32x32 output layout).
+#include "gain.hpp"
+
+namespace dgfs {
+namespace mfma {
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef float f8v __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+
+constexpr int N = 32;
+constexpr int NT = 512;
+constexpr int PST = 1032;                  // LDS plane stride of the x-contracted field (halves)
+constexpr int VS = 36;                     // LDS row stride of the per-plane vectors (floats)
+constexpr int TABH = 3 * 2 * 2 * 64 * 8;   // halves per field table: [X, Z, Y][c or s][hi, lo][lane][8]
+constexpr int PREPH = 2 * 32768 + 2048;    // halves per (node, species): f hi, f lo, a_x hi, a_x lo
+constexpr int AUX = 64;                    // floats per (node, species) after the halves
+static_assert(size_t(PREPH) * 2 + AUX * 4 == mfma_prep_bytes, "prepared-input layout");
+
+struct Args {
+    const float* f;        // [nb][s][N^3] input (x-major, z fastest)
+    _Float16* prep;        // [nb][s]: PREPH halves then AUX floats (mfma_prep_bytes each)
+    const _Float16* tab;   // [dirs][nrho][2 fields][TABH]
+    const float* sc;       // [dirs][nrho][2 fields][4]: s_x, s_y, s_z
+    const int* cls;        // [ncls][4] = i, j, ndir, dir_offset
+    const float* wdir;     // [ncls]
+    cx<float>* P;          // chunk partials, as gain_kernel<float, 32, 2, 1>
+    int s, ncls, nrho, nb;
+};
+
+__device__ __forceinline__ const _Float16* prep_h(const Args& a, int fs) {
+    return reinterpret_cast<const _Float16*>(reinterpret_cast<const char*>(a.prep) + size_t(fs) * mfma_prep_bytes);
+}
+__device__ __forceinline__ const float* prep_aux(const Args& a, int fs) {
+    return reinterpret_cast<const float*>(reinterpret_cast<const char*>(a.prep) + size_t(fs) * mfma_prep_bytes +
+                                          size_t(PREPH) * 2);
+}
+
+// v = hi + lo, hi = f16(v), lo = f16(v - hi): the residual is formed and rounded by one
+// mixed-precision FMA per value (v_fma_mixlo/hi_f16 each write one half of the result).
+__device__ __forceinline__ unsigned mix_lo2(unsigned hp, float v0, float v1) {
+    unsigned r;
+    asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(hp), "v"(v0));
+    asm("v_fma_mixhi_f16 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(r) : "v"(hp), "v"(v1));
+    return r;
+}
+__device__ __forceinline__ void split8(f8v v, h8& hi, h8& lo) {
+    hi = __builtin_convertvector(v, h8);
+    const u4v hp = __builtin_bit_cast(u4v, hi);
+    u4v lp;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) lp[k] = mix_lo2(hp[k], v[2 * k], v[2 * k + 1]);
+    lo = __builtin_bit_cast(h8, lp);
+}
+__device__ __forceinline__ void split4(f4v v, h4& hi, h4& lo) {
+    hi = __builtin_convertvector(v, h4);
+    const u2v hp = __builtin_bit_cast(u2v, hi);
+    u2v lp;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) lp[k] = mix_lo2(hp[k], v[2 * k], v[2 * k + 1]);
+    lo = __builtin_bit_cast(h4, lp);
+}
+__device__ __forceinline__ h8 ld8(const _Float16* p) { return *reinterpret_cast<const h8*>(p); }
+
+#define MF32(a, b, c) __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0)
+#define MF16(a, b, c) __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0)
+
+// ------------------------------------------------------------------ input preparation
+// One workgroup per (node, species): the scale 2^k, f hi/lo transposed to [col = (y, z)][x]
+// (the A operand of the x-contraction), a_x = sum_x (-1)^x f as hi/lo [y][z], then
+// a_xz(y) = sum_z (-1)^z a_x(y, z) with its own scale, a_xyz, and 2^-k.
+// aux: [0, 32) a_xz(y) * 2^-j, [32] a_xyz, [33] 2^-k, [34] 2^j.
+__global__ __launch_bounds__(256) void prep_kernel(Args a) {
+    const int fs = blockIdx.x, tid = threadIdx.x;
+    const float* f = a.f + size_t(fs) * (N * N * N);
+    _Float16* out = reinterpret_cast<_Float16*>(reinterpret_cast<char*>(a.prep) + size_t(fs) * mfma_prep_bytes);
+    float* aux = reinterpret_cast<float*>(out + PREPH);
+    __shared__ float red[256];
+    __shared__ float ax[N * N];
+    __shared__ float axz[N];
+    float mx = 0.f;
+    for (int i = tid; i < N * N * N; i += 256) mx = fmaxf(mx, fabsf(f[i]));
+    red[tid] = mx;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (tid < k) red[tid] = fmaxf(red[tid], red[tid + k]);
+        __syncthreads();
+    }
+    const float M = red[0];
+    int e = 0;
+    if (M > 0.f && M <= 3.0e38f) (void)frexpf(M, &e);   // M = m 2^e, m in [0.5, 1)
+    const int k = (M > 0.f && M <= 3.0e38f) ? max(-120, min(120, 8 - e)) : 0;
+    const float scale = ldexpf(1.f, k);
+    for (int col = tid; col < N * N; col += 256) {
+        const int y = col >> 5, z = col & 31;
+        float acc = 0.f;
+#pragma unroll
+        for (int xb = 0; xb < 4; ++xb) {
+            f8v v;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int x = 8 * xb + j;
+                v[j] = f[(x * N + y) * N + z] * scale;
+                acc += (x & 1) ? -v[j] : v[j];
+            }
+            h8 hi, lo;
+            split8(v, hi, lo);
+            *reinterpret_cast<h8*>(out + col * 32 + 8 * xb) = hi;
+            *reinterpret_cast<h8*>(out + 32768 + col * 32 + 8 * xb) = lo;
+        }
+        ax[col] = acc;
+        const _Float16 h = _Float16(acc);
+        out[65536 + col] = h;
+        out[65536 + 1024 + col] = _Float16(acc - float(h));
+    }
+    __syncthreads();
+    if (tid < N) {
+        float acc = 0.f;
+        for (int z = 0; z < N; ++z) acc += (z & 1) ? -ax[tid * N + z] : ax[tid * N + z];
+        axz[tid] = acc;
+    }
+    __syncthreads();
+    __shared__ float colscale;
+    if (tid == 0) {
+        float axyz = 0.f, am = 0.f;
+        for (int y = 0; y < N; ++y) {
+            axyz += (y & 1) ? -axz[y] : axz[y];
+            am = fmaxf(am, fabsf(axz[y]));
+        }
+        int ej = 0;
+        if (am > 0.f && am <= 3.0e38f) (void)frexpf(am, &ej);
+        colscale = ldexpf(1.f, (am > 0.f && am <= 3.0e38f) ? max(-120, min(120, 8 - ej)) : 0);
+        aux[32] = axyz;
+        aux[33] = ldexpf(1.f, -k);
+        aux[34] = colscale;
+    }
+    __syncthreads();
+    if (tid < N) aux[tid] = axz[tid] * colscale;
+}
+
+// ------------------------------------------------------------------ gain kernel
+struct Lds {
+    _Float16 G1[2][2][16 * PST];   // x-contracted field [buffer][hi, lo][plane]: rows y, 16-byte
+                                   // blocks of z rotated by y/4 (conflict-free row reads)
+    float V[2][17 * VS];           // [buffer]: v_m(y) = sum_z (-1)^z (C_x f)(x_m, y, z), then a_xz(y)
+    float W[8][2][3 * VS];         // per wavefront and field: C_y v_2w, C_y v_2w+1, C_y a_xz
+    float Px[3][4 * 64 * 4];       // P_x in the output layout, three fields in flight
+    float Lxy[3][32];
+};
+static_assert(sizeof(Lds) <= 160 * 1024, "LDS");
+
+__device__ __forceinline__ int g1off(int m, int y, int blk) { return m * PST + y * 32 + ((blk + (y >> 2)) & 3) * 8; }
+
+// P_x = C_y C_z a_x in the output layout and L_xy = C_z a_xy of one field (one wavefront).
+__device__ __forceinline__ void alpha_plane(const Args& a, int fs, int tb, Lds& L, int pb) {
+    const int l = threadIdx.x & 63, h = l >> 5, l32 = l & 31;
+    const _Float16* T = a.tab + size_t(tb) * TABH;
+    const _Float16* aH = prep_h(a, fs) + 65536;
+    const _Float16* aL = aH + 1024;
+    f16v dA = {};
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const h8 bzh = ld8(T + ((1 * 2 + s) * 2 + 0) * 512 + l * 8), bzl = ld8(T + ((1 * 2 + s) * 2 + 1) * 512 + l * 8);
+        const h8 ah = ld8(aH + l32 * 32 + 16 * s + 8 * h), al = ld8(aL + l32 * 32 + 16 * s + 8 * h);
+        dA = MF32(ah, bzh, dA);
+        dA = MF32(ah, bzl, dA);
+        dA = MF32(al, bzh, dA);
+    }
+    float a1 = 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) a1 += (r & 1) ? -dA[r] : dA[r];
+    a1 += __shfl_xor(a1, 32);
+    if (h == 0) L.Lxy[pb][l32] = a1;
+    f16v px = {};
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const h8 tyh = ld8(T + ((2 * 2 + s) * 2 + 0) * 512 + l * 8), tyl = ld8(T + ((2 * 2 + s) * 2 + 1) * 512 + l * 8);
+        f8v va;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) va[e] = dA[8 * s + e];
+        h8 ph, pl;
+        split8(va, ph, pl);
+        px = MF32(tyh, ph, px);
+        px = MF32(tyh, pl, px);
+        px = MF32(tyl, ph, px);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        *reinterpret_cast<f4v*>(&L.Px[pb][(j * 64 + l) * 4]) = f4v{px[4 * j], px[4 * j + 1], px[4 * j + 2], px[4 * j + 3]};
+}
+
+// What the first field of a direction leaves for the second: its contracted values T and
+// the per-plane pieces of its corrections (P_z, L_xz stay in the wavefront's LDS area,
+// P_x and L_xy in their buffer).
+struct FieldState {
+    f16v T[2];
+    float py[2], lyz[2];
+    float sx, sy, sz, pnt;
+};
+
+// One shifted field for chunk c.  fs: (node, species) index of the input, tb: table index,
+// bf: LDS buffer (0: first field of the direction, 1: second), pb/pbA: P_x buffers of this
+// field and of the direction's first field.  The wavefront nxt_wave prepares the next
+// field's P_x.  ACC = false keeps the field in st; ACC = true accumulates
+// S += wgt (Re A Re B - Im A Im B) with A from st and B this field.
+template <bool ACC>
+__device__ __forceinline__ void shift_field(const Args& a, int fs, int tb, int c, Lds& L, int bf, int pb, int pbA,
+                                            FieldState& st, int nxt_wave, int nxt_fs, int nxt_tb, float (*S)[16],
+                                            float wgt) {
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, h = l >> 5, g = l >> 4, mm = l & 15, l32 = l & 31;
+    const _Float16* fH = prep_h(a, fs);
+    const _Float16* fL = fH + 32768;
+    const _Float16* T = a.tab + size_t(tb) * TABH;
+    const float sx = a.sc[4 * tb], sy = a.sc[4 * tb + 1], sz = a.sc[4 * tb + 2];
+    // ---- x-contraction: G1[m][y][z] = sum_x' C_x[2m + c][x'] f[x'][y][z]; 16x16x32 tiles
+    // of 16 (y, z) columns, lane (m = l%16, g = l/16) keeping z = 16 tt + 4 g + r.  The G1
+    // buffer bf was last read by the field before the previous one, whose readers all
+    // passed the previous field's barrier, so each tile is written as it completes.
+    const h8 bxh = ld8(T + ((0 * 2 + c) * 2 + 0) * 512 + l * 8), bxl = ld8(T + ((0 * 2 + c) * 2 + 1) * 512 + l * 8);
+    _Float16* GH = L.G1[bf][0];
+    _Float16* GL = L.G1[bf][1];
+#pragma unroll
+    for (int yi = 0; yi < 4; ++yi) {
+        const int y = 4 * w + yi;
+        float vpart = 0.f;
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            const int col = y * 32 + 16 * tt + mm;
+            const h8 ah = ld8(fH + col * 32 + 8 * g), al = ld8(fL + col * 32 + 8 * g);
+            f4v acc = {};
+            acc = MF16(ah, bxh, acc);
+            acc = MF16(ah, bxl, acc);
+            acc = MF16(al, bxh, acc);
+            vpart += acc[0] - acc[1] + acc[2] - acc[3];
+            h4 hi, lo;
+            split4(acc, hi, lo);
+            const int o = g1off(mm, y, 2 * tt + (g >> 1)) + 4 * (g & 1);
+            *reinterpret_cast<h4*>(&GH[o]) = hi;
+            *reinterpret_cast<h4*>(&GL[o]) = lo;
+        }
+        vpart += __shfl_xor(vpart, 16);
+        vpart += __shfl_xor(vpart, 32);
+        if (g == 0) L.V[bf][mm * VS + y] = vpart;
+    }
+    const float* aux = prep_aux(a, fs);
+    if (w == 1 && l < 32) L.V[bf][16 * VS + l] = aux[l];
+    h8 bzh[2], bzl[2], tyh[2], tyl[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        bzh[s] = ld8(T + ((1 * 2 + s) * 2 + 0) * 512 + l * 8);
+        bzl[s] = ld8(T + ((1 * 2 + s) * 2 + 1) * 512 + l * 8);
+        tyh[s] = ld8(T + ((2 * 2 + s) * 2 + 0) * 512 + l * 8);
+        tyl[s] = ld8(T + ((2 * 2 + s) * 2 + 1) * 512 + l * 8);
+    }
+    __syncthreads();
+    // one wavefront prepares the next field's P_x (its buffer was last read before this
+    // barrier)
+    if (w == nxt_wave) alpha_plane(a, nxt_fs, nxt_tb, L, (pb + 1) % 3);
+    // ---- C_y [v_2w | v_2w+1 | a_xz]: this wavefront's P_z(x_m, y) and L_xz(y); L_yz(x_m)
+    float lyz0, lyz1;
+    {
+        const int n = l32;
+        const int row = n == 0 ? 2 * w : n == 1 ? 2 * w + 1 : 16;
+        f16v d = {};
+        float ly = 0.f;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            f8v v = {};
+            if (n < 3) {
+                const float* src = &L.V[bf][row * VS + 16 * s + 4 * h];
+                const f4v v0 = *reinterpret_cast<const f4v*>(src), v1 = *reinterpret_cast<const f4v*>(src + 8);
+                v = f8v{v0[0], v0[1], v0[2], v0[3], v1[0], v1[1], v1[2], v1[3]};
+                ly += v0[0] - v0[1] + v0[2] - v0[3] + v1[0] - v1[1] + v1[2] - v1[3];
+            }
+            h8 bh, bl;
+            split8(v, bh, bl);
+            d = MF32(tyh[s], bh, d);
+            d = MF32(tyh[s], bl, d);
+            d = MF32(tyl[s], bh, d);
+        }
+        ly += __shfl_xor(ly, 32);
+        lyz0 = __builtin_amdgcn_readlane(ly, 0);
+        lyz1 = __builtin_amdgcn_readlane(ly, 1);
+        if (n < 3) {
+            const float un = n == 2 ? aux[34] : 1.f;   // the a_xz column was stored times 2^j
+            const float inv = 1.f / un;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                *reinterpret_cast<f4v*>(&L.W[w][bf][n * VS + 8 * j + 4 * h]) =
+                    f4v{d[4 * j] * inv, d[4 * j + 1] * inv, d[4 * j + 2] * inv, d[4 * j + 3] * inv};
+        }
+    }
+    // ---- z- then y-contraction of this wavefront's two planes
+    f16v d2[2];
+    float py[2];
+#pragma unroll
+    for (int pi = 0; pi < 2; ++pi) {
+        f16v d1 = {};
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int o = g1off(2 * w + pi, l32, 2 * s + h);
+            const h8 ah = ld8(GH + o), al = ld8(GL + o);
+            d1 = MF32(ah, bzh[s], d1);
+            d1 = MF32(ah, bzl[s], d1);
+            d1 = MF32(al, bzh[s], d1);
+        }
+        float a1 = 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) a1 += (r & 1) ? -d1[r] : d1[r];
+        py[pi] = a1 + __shfl_xor(a1, 32);   // P_y(x_m, z) = sum_y (-1)^y (C_x C_z f)
+        d2[pi] = f16v{};
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            f8v v;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = d1[8 * s + e];
+            h8 bh, bl;
+            split8(v, bh, bl);
+            d2[pi] = MF32(tyh[s], bh, d2[pi]);
+            d2[pi] = MF32(tyh[s], bl, d2[pi]);
+            d2[pi] = MF32(tyl[s], bh, d2[pi]);
+        }
+    }
+    // ---- corrections (signs: u_x = (-1)^c for every plane of the chunk, u_y by the row's
+    // parity r%2, u_z by the lane's parity)
+    const float ux = (c & 1) ? -1.f : 1.f, uz = (l & 1) ? -1.f : 1.f;
+    const float pnt = sx * sy * sz * ux * uz * aux[32];
+    if constexpr (!ACC) {
+        st.T[0] = d2[0];
+        st.T[1] = d2[1];
+        st.py[0] = py[0];
+        st.py[1] = py[1];
+        st.lyz[0] = lyz0;
+        st.lyz[1] = lyz1;
+        st.sx = sx;
+        st.sy = sy;
+        st.sz = sz;
+        st.pnt = pnt;
+    } else {
+        const float cB = sx * sz * ux * uz, K1 = sx * ux, K3 = sz * uz;
+        const float cBA = st.sx * st.sz * ux * uz, K1A = st.sx * ux, K3A = st.sz * uz;
+#pragma unroll
+        for (int pi = 0; pi < 2; ++pi) {
+            const float reE = sx * sy * ux * L.Lxy[pb][l32] + sy * sz * uz * (pi == 0 ? lyz0 : lyz1);
+            const float imE = sy * py[pi] - pnt;
+            const float reEA = st.sx * st.sy * ux * L.Lxy[pbA][l32] + st.sy * st.sz * uz * st.lyz[pi];
+            const float imEA = st.sy * st.py[pi] - st.pnt;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const f4v lxz = *reinterpret_cast<const f4v*>(&L.W[w][bf][2 * VS + 8 * j + 4 * h]);
+                const f4v pz = *reinterpret_cast<const f4v*>(&L.W[w][bf][pi * VS + 8 * j + 4 * h]);
+                const f4v lxzA = *reinterpret_cast<const f4v*>(&L.W[w][bf ^ 1][2 * VS + 8 * j + 4 * h]);
+                const f4v pzA = *reinterpret_cast<const f4v*>(&L.W[w][bf ^ 1][pi * VS + 8 * j + 4 * h]);
+                const f4v px = *reinterpret_cast<const f4v*>(&L.Px[pb][(j * 64 + l) * 4]);
+                const f4v pxA = *reinterpret_cast<const f4v*>(&L.Px[pbA][(j * 64 + l) * 4]);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 4 * j + i;
+                    const float sgn = (i & 1) ? -1.f : 1.f;
+                    const float rv = d2[pi][r] - sgn * reE - cB * lxz[i];
+                    const float iv = K1 * px[i] + sgn * imE + K3 * pz[i];
+                    const float rA = st.T[pi][r] - sgn * reEA - cBA * lxzA[i];
+                    const float iA = K1A * pxA[i] + sgn * imEA + K3A * pzA[i];
+                    S[pi][r] = fmaf(wgt, fmaf(-iA, iv, rA * rv), S[pi][r]);
+                }
+            }
+        }
+    }
+}
+
+union alignas(16) Smem {
+    Lds m;
+    cx<float> buf[GainK<float, N, 2, 1>::LDS];
+};
+
+__global__ __launch_bounds__(NT) void gain_kernel(Args a) {
+    __shared__ Smem sm;
+    Lds& L = sm.m;
+    // work items of one node on one XCD (as gain_kernel)
+    const int ipn = a.ncls * a.nrho * 2;
+    const int gi = blockIdx.x;
+    const int xcd = gi & 7, local = gi >> 3;
+    const int b = (local / ipn) * 8 + xcd;
+    if (b >= a.nb) return;
+    int item = local % ipn;
+    const int c = item % 2;
+    item /= 2;
+    const int q = item % a.nrho;
+    const int cl = item / a.nrho;
+    const int ci = a.cls[4 * cl], cj = a.cls[4 * cl + 1], ndir = a.cls[4 * cl + 2], doff = a.cls[4 * cl + 3];
+    const int fA = b * a.s + ci, fB = b * a.s + cj;
+    const float wgt = a.wdir[cl] * prep_aux(a, fA)[33] * prep_aux(a, fB)[33];
+    const int w = threadIdx.x >> 6;
+    auto tab = [&](int d, int fld) { return ((doff + d) * a.nrho + q) * 2 + fld; };
+    float S[2][16];
+#pragma unroll
+    for (int pi = 0; pi < 2; ++pi)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) S[pi][r] = 0.f;
+    if (w == 0) alpha_plane(a, fA, tab(0, 0), L, 0);
+#pragma unroll 1
+    for (int d = 0; d < ndir; ++d) {
+        FieldState st;
+        const int k = 2 * d;
+        shift_field<false>(a, fA, tab(d, 0), c, L, 0, k % 3, 0, st, (k + 1) % 8, fB, tab(d, 1), S, 0.f);
+        shift_field<true>(a, fB, tab(d, 1), c, L, 1, (k + 1) % 3, k % 3, st, d + 1 < ndir ? (k + 2) % 8 : -1, fA,
+                          tab(d + 1 < ndir ? d + 1 : d, 0), S, wgt);
+    }
+    __syncthreads();  // every wavefront is done with the contraction buffers
+    // S_q to LDS as rows (plane m, y) of z values, then the forward transform of gain_kernel
+    using K = GainK<float, N, 2, 1>;
+    {
+        const int l = threadIdx.x & 63, h = l >> 5;
+#pragma unroll
+        for (int pi = 0; pi < 2; ++pi)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int y = 8 * (r / 4) + 4 * h + r % 4;
+                sm.buf[((2 * w + pi) * N + y) * K::ROW + (l & 31)] = cx<float>{S[pi][r], 0.f};
+            }
+    }
+    __syncthreads();
+    cx<float>* Pq = a.P + ((int64_t(b) * a.ncls + cl) * a.nrho + q) * int64_t(2) * K::NP * K::NPEN;
+    store_partial<float, N, 2, 1, false>(sm.buf, Pq, c);
+}
+
+}  // namespace mfma
+
+hipError_t launch_gain_mfma32(const dgfs_plan& p, const float* f, cx<float>* P, void* prep, int nb, hipStream_t st) {
+    const char* dev = static_cast<const char*>(p.dev);
+    mfma::Args a;
+    a.f = f;
+    a.prep = static_cast<_Float16*>(prep);
+    a.tab = reinterpret_cast<const _Float16*>(dev + p.off_mtab);
+    a.sc = reinterpret_cast<const float*>(dev + p.off_msc);
+    a.cls = reinterpret_cast<const int*>(dev + p.off_cls);
+    a.wdir = reinterpret_cast<const float*>(dev + p.off_wdir);
+    a.P = P;
+    a.s = p.s;
+    a.ncls = int(p.classes.size());
+    a.nrho = p.nrho;
+    a.nb = nb;
+    mfma::prep_kernel<<<dim3(unsigned(int64_t(nb) * p.s)), dim3(256), 0, st>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t ipn = int64_t(a.ncls) * p.nrho * 2;
+    const int64_t groups = ((nb + 7) / 8) * 8 * ipn;
+    mfma::gain_kernel<<<dim3(unsigned(groups)), dim3(mfma::NT), 0, st>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace dgfs

@@ -136,9 +136,11 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Compiled gain-kernel geometries (CH, CZ) per N and precision; the first is the default
 // (the fastest measured on MI355X for that N; autotune.py re-measures on the device).
+// (32, 2, 0): the matrix-core gain (FP32 VHS plans of the circular form; the others get
+// the first geometry with CZ > 0).
 // N = 36 and 72 are the padded grids of the dealiased form at N = 24 and 48 only.
 constexpr int kTilesF32[][3] = {{16, 1, 1}, {16, 2, 1}, {16, 1, 2}, {24, 3, 1}, {24, 3, 2}, {24, 3, 4},
-                                {32, 2, 1}, {32, 4, 1}, {32, 4, 2}, {48, 6, 2}, {48, 12, 4}, {48, 12, 2},
+                                {32, 2, 0}, {32, 2, 1}, {32, 4, 1}, {32, 4, 2}, {48, 6, 2}, {48, 12, 4}, {48, 12, 2},
                                 {64, 16, 4}, {36, 3, 2}, {72, 24, 4}};
 constexpr int kTilesF64[][3] = {{16, 1, 1}, {24, 3, 2}, {32, 4, 2}, {48, 12, 4}, {64, 32, 8}, {36, 6, 4},
                                 {72, 72, 8}};
@@ -156,7 +158,16 @@ int tile_candidates(int N, int precision, GainGeometry* out, int max) {
     return n;
 }
 
-bool gain_geometry(int N, int precision, GainGeometry* g) { return tile_candidates(N, precision, g, 1) == 1; }
+bool gain_geometry(int N, int precision, GainGeometry* g, bool matrix_ok) {
+    GainGeometry cand[16];
+    const int n = tile_candidates(N, precision, cand, 16);
+    for (int k = 0; k < n; ++k)
+        if (cand[k].CZ != 0 || matrix_ok) {
+            *g = cand[k];
+            return true;
+        }
+    return false;
+}
 
 hipError_t launch_collide(const dgfs_plan& p, const void* f, void* Q, int64_t nb, void* ws, bool pairs,
                           hipStream_t st, hipEvent_t* ev) {

@@ -15,13 +15,19 @@ namespace dgfs {
 // Launch geometry of the fused gain kernel for one velocity resolution N:
 // CH   chunks of the output grid along x (each work item owns x-indices = c mod CH),
 // CZ   thread groups sharing each y/z pencil of the chunk (group g keeps the outputs
-//      with index = g mod CZ).
+//      with index = g mod CZ); CZ = 0: the shifted fields are formed on the matrix cores
+//      (gain_mfma.hip).
 struct GainGeometry {
     int CH;
     int CZ;
 };
 
-bool gain_geometry(int N, int precision, GainGeometry* g);            // the default
+// The default: the first compiled geometry, skipping the matrix-core ones (CZ = 0: FP32
+// VHS plans of the circular form) unless matrix_ok.
+bool gain_geometry(int N, int precision, GainGeometry* g, bool matrix_ok = true);
+// Bytes per (node, species) of the matrix-core gain's prepared input (N = 32): f split into
+// FP16 hi and lo, the alternating x-sum plane split likewise, and 64 FP32 scalars.
+constexpr size_t mfma_prep_bytes = (2 * 32768 + 2048) * 2 + 64 * 4;
 int tile_candidates(int N, int precision, GainGeometry* out, int max);  // compiled geometries
 
 // One "gain class": the S_q field sum_p w A_p B_p with A = f^i shifted by +a rho sigma_p,
@@ -80,6 +86,9 @@ struct dgfs_plan {
     size_t dev_bytes = 0;
     // byte offsets of the tables in `dev`
     size_t off_kx = 0, off_yz = 0, off_nyq = 0, off_F = 0, off_G = 0, off_tw = 0, off_cls = 0, off_wdir = 0;
+    // matrix-core gain (geometry CZ = 0): split-FP16 shift-matrix operands and Nyquist
+    // coefficients per (direction, rho, field)
+    size_t off_mtab = 0, off_msc = 0;
     size_t off_minv = 0;  // (s+4)^2 doubles, inverse Gram matrix of the invariants
     // plain per-point FP64 path (FP64 plans only): phases [s*s][nrho][M][2][3][N], F [s*s][nrho][K2]
     size_t off_plain_ph = 0, off_plain_F = 0;

@@ -143,12 +143,23 @@ def test_tile_candidates_and_validation():
         c64 = tile_candidates(N, "f64")
         assert len(c32) >= 1 and len(c64) >= 1
         for ch, cz in c32:
+            if cz == 0:   # the matrix-core gain: N = 32, two x-chunks
+                assert (N, ch) == (32, 2)
+                continue
             assert N % ch == 0 and N % cz == 0 and ((N // ch) * N) % 64 == 0
+        assert all(cz > 0 for _, cz in c64)
     m = (1.0, 2.0)
     k = _kern(m, 0.74)
     for tile in tile_candidates(32, "f32"):
         assert check_problem(m, 6.0, 32, 12, 16, k, tile=tile) == DGFS_OK
     assert check_problem(m, 6.0, 32, 12, 16, k, tile=(3, 1)) == DGFS_EUNSUPPORTED
+    # the matrix-core geometry: FP32, N = 32, VHS kernels only
+    from paper_1903_03056_amd import vss_kernel as _vss
+    assert tile_candidates(32, "f32")[0] == (2, 0)
+    assert check_problem(m, 6.0, 32, 12, 16, _vss(m, 0.8, 1.4), tile=(2, 0)) == DGFS_EUNSUPPORTED
+    assert check_problem(m, 6.0, 32, 12, 16, _vss(m, 0.8, 1.4)) == DGFS_OK
+    assert check_problem(m, 6.0, 32, 12, 16, k, precision="f64", tile=(2, 0)) == DGFS_EUNSUPPORTED
+    assert check_problem(m, 6.0, 16, 6, 8, k, tile=(2, 0)) == DGFS_EUNSUPPORTED
     # N = 64: VHS kernels on one or several grids; no VSS kernels, no dealiased form
     from paper_1903_03056_amd import vss_kernel
     assert check_problem(m, 12.0, 64, 6, 32, k) == DGFS_OK
