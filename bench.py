@@ -40,6 +40,7 @@ sys.path.insert(0, ROOT)
 WORKLOAD = dict(batch=256, masses=(1.0, 2.0), omega=0.74, N=32, L=6.0, M=12, n_rho=16, noise=1e-2, seed=2)
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
 PEAK_HBM_GBPS = 8000.0
+PEAK_FP16_MFMA_TFLOPS = 2500.0    # dense FP16 matrix cores
 
 
 def log(*a):
@@ -73,6 +74,18 @@ def gain_flops_per_node_vss(N, M, n_rho, s, antipodal=True):
     fft = 5.0 * n3 * math.log2(n3)
     dirs = s * (M // 2) + (s * (s - 1) // 2) * M if antipodal else s * s * M
     return dirs * n_rho * (2 * (fft + 6 * n3) + 12 * n3 + fft)
+
+
+def mfma_flops_per_launch(batch, N, M, n_rho, s):
+    """Matrix-core flops the (2, 0) gain geometry executes per launch: per work item (node,
+    class, rho_q, x-chunk) and field, the x-contraction (8 wavefronts x 8 tiles x 3 split
+    products of 16x16x32), the per-wavefront C_y product of the plane vectors (6 of
+    32x32x16), the two planes' z- and y-contractions (8 x 2 x 12) and the a_x plane (12);
+    two fields per direction, two chunks."""
+    assert N == 32
+    per_field = 8 * 8 * 3 * 16384 + 8 * 6 * 32768 + 8 * 2 * 12 * 32768 + 12 * 32768
+    class_dirs = s * (M // 2) + s * (s - 1) // 2 * M   # antipodal design
+    return batch * class_dirs * n_rho * 2 * 2 * per_field
 
 
 def load_traffic():
@@ -520,7 +533,7 @@ def main():
 
     import torch
 
-    from paper_1903_03056_amd import CollisionPlan
+    from paper_1903_03056_amd import CollisionPlan, tile_candidates
     from synth import inputs as I
 
     if args.only_leg == "vss_slab":
@@ -609,6 +622,7 @@ def main():
     gain_ms = stage_avg[1]
     flop_node = gain_flops_per_node(w["N"], w["M"], w["n_rho"], s)
     achieved = flop_node * w["batch"] / (gain_ms / 1e3) / 1e12
+    geometry = tuple(plan.tile) if plan.tile else tuple(tile_candidates(w["N"], "f32")[0])
     traffic = load_traffic()
     cons_avg = float(np.mean(cons_ms))
     cons_bytes = w["batch"] * s * w["N"] ** 3 * (4 + 8)
@@ -636,16 +650,26 @@ def main():
         "stages_ms": {"forward_fft": round(stage_avg[0], 4), "gain": round(stage_avg[1], 4),
                       "radial_loss": round(stage_avg[2], 4), "inverse_xy": round(stage_avg[3], 4),
                       "inverse_z_combine": round(stage_avg[4], 4), "conserve_fp64": round(cons_avg, 4)},
-        "roofline": {"bound": "alu", "kernel": "gain_kernel", "achieved": round(achieved, 3),
+        "roofline": {"bound": "mfma" if geometry[1] == 0 else "alu",
+                     "kernel": "mfma::gain_kernel" if geometry[1] == 0 else "gain_kernel",
+                     "geometry": list(geometry), "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-                     "traffic": traffic, "flop_per_launch": flop_node * w["batch"]},
+                     "traffic": traffic, "flop_per_launch": flop_node * w["batch"],
+                     "flop_model": "the FP32 work of the spectral gain (FFT model), against the FP32 "
+                                   "peak (vector = matrix, 157.3 TFLOP/s)"},
         "conserve_roofline": {"bound": "hbm", "achieved": round(cons_gbps, 1), "peak": PEAK_HBM_GBPS,
                               "unit": "GB/s", "frac": round(cons_gbps / PEAK_HBM_GBPS, 4),
                               "bytes_per_launch": cons_bytes},
         "precompute_s": round(precompute_s, 3),
         "rel_linf_vs_stored_oracle_samples": stored_oracle_errors("slab_N32", Q),
     }
+    if geometry[1] == 0:
+        mf = mfma_flops_per_launch(w["batch"], w["N"], w["M"], w["n_rho"], s)
+        out["roofline"]["matrix_cores"] = {
+            "executed_flop_per_launch": mf, "achieved": round(mf / (gain_ms / 1e3) / 1e12, 1),
+            "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s (FP16 dense, the split products)",
+            "frac": round(mf / (gain_ms / 1e3) / 1e12 / PEAK_FP16_MFMA_TFLOPS, 4)}
     Qh = Q.double().cpu().numpy()
     Qch = Qc[:4].cpu().numpy()
     # the plain per-point FP64 GPU path on the first nodes of the same workload

@@ -24,11 +24,11 @@ COPY_BYTES = 256 * 1024 * 1024
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
-GAIN_SOURCES = ("gain.hpp", "fft.hpp", "passes.hpp", "tiles_32.hip")
+GAIN_SOURCES = ("gain.hpp", "fft.hpp", "passes.hpp", "tiles_32.hip", "gain_mfma.hip")
 
 
 def gain_source_digest() -> str:
-    """SHA-256 over the sources the N=32 gain kernel is compiled from."""
+    """SHA-256 over the sources the N=32 gain kernels (FFT and matrix-core) are compiled from."""
     h = hashlib.sha256()
     for name in GAIN_SOURCES:
         with open(os.path.join(ROOT, "paper_1903_03056_amd", "csrc", name), "rb") as fh:
@@ -82,10 +82,10 @@ def main(trace_dir, fetch_dir, write_dir, prefix, command):
                 continue
             fh.write(f"| `{short(k)}` | {fv / 2**20:.1f} | {wv / 2**20:.1f} | {fv * ff / 2**20:.1f} | "
                      f"{wv * fw / 2**20:.1f} |\n")
-    gain = [(fv, wv) for (k, fv), (k2, wv) in zip(fetch, write) if "gain_kernel" in k and k == k2]
+    gain = [(k, fv, wv) for (k, fv), (k2, wv) in zip(fetch, write) if "gain_kernel" in k and k == k2]
     if gain:
-        fv, wv = gain[-1]
-        rec = {"kernel": "gain_kernel<float, 32, ...>",
+        kname, fv, wv = gain[-1]
+        rec = {"kernel": short(kname),
                "workload": "256-node N=32 slab (bench.py)",
                "bytes_per_launch": fv * ff + wv * fw,
                "read_bytes": fv * ff, "write_bytes": wv * fw,
