@@ -99,7 +99,12 @@ typedef struct {
     int32_t tile_ch, tile_cz;        /* gain-kernel geometry: x-chunks per field and thread
                                         groups per y/z pencil; 0, 0 = the library's default
                                         for (N, precision); other values must be one of
-                                        dgfs_tile_candidates (DGFS_EUNSUPPORTED otherwise) */
+                                        dgfs_tile_candidates (DGFS_EUNSUPPORTED otherwise).
+                                        cz = 0 (with ch = 2, FP32, N = 32): the shifted fields
+                                        of Sec. 4 are formed on the matrix cores as dense shift
+                                        contractions with FP16 hi/lo operands and FP32 sums;
+                                        VHS kernels (alpha = 1) and the circular form only, and
+                                        the default for such problems. */
     int32_t dealias;                 /* 0: eq. (sum) as the circular convolution the FFT
                                         evaluation computes on the N^3 grid; 1: l + m = k
                                         taken literally (no wrap-around), evaluated with
@@ -285,7 +290,8 @@ dgfs_status dgfs_kernel_mode(double alpha, double gamma, double C, double a, dou
                              const double* sigma, double* F);
 
 /* Gain-kernel geometries compiled for (N, precision), as pairs (ch, cz) in
- * pairs[2*k], pairs[2*k+1], k < *count <= max_pairs; the first is the default. */
+ * pairs[2*k], pairs[2*k+1], k < *count <= max_pairs; the first is the default (for VSS
+ * kernels or the dealiased form: the first with cz > 0). */
 dgfs_status dgfs_tile_candidates(int32_t N, int32_t precision, int32_t* pairs, int32_t max_pairs,
                                  int32_t* count);
 
