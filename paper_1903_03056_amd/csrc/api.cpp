@@ -307,18 +307,16 @@ void push_uses(dgfs::SlotSet& S, int ncls, std::vector<char>& blob) {
     push_int(blob, S.off_cuses, S.cuses);
 }
 
-// Matrix-core gain tables (geometry CZ = 0: FP32 VHS plans at N = 32).  Per (direction,
-// rho, field) the operands of the three shift contractions, every entry split into FP16
-// hi and lo, in the MFMA lane layouts the kernel reads ([x, z, y][chunk or k-step][hi,
-// lo][lane][8]), and the Nyquist coefficients s = -sin(N theta / 2) / N.  The real part of
-// the shift matrix is circulant, C(n, m) = c((n - m) mod N) with
-// c(d) = (1/N) sum_{l=-N/2}^{N/2-1} cos(l (2 pi d / N + theta)); theta as for the phases.
+// Matrix-core gain tables (geometry CZ = 0: FP32 VHS plans at N = 32).  The real part of
+// each axis's shift matrix is circulant, C(n, m) = c((n - m) mod N) with
+// c(d) = (1/N) sum_{l=-N/2}^{N/2-1} cos(l (2 pi d / N + theta)), theta as for the phases.
+// Per (direction, rho, field) and axis x, y, z: r(j) = c(-j mod N) for j < N, each as one
+// word FP16 hi | FP16 lo << 16 (hi = f16(v), lo = f16(v - hi), v = float(r(j))); then the
+// Nyquist coefficients s = -sin(N theta / 2) / N of the three axes.
 void build_mfma_tables(dgfs_plan& P, std::vector<char>& blob) {
     const int N = P.N, nrho = P.nrho;
-    constexpr size_t TABH = 3 * 2 * 2 * 64 * 8;
-    std::vector<_Float16> tab(size_t(P.total_dirs) * nrho * 2 * TABH);
+    std::vector<uint32_t> tab(size_t(P.total_dirs) * nrho * 2 * 3 * N);
     std::vector<double> sc(size_t(P.total_dirs) * nrho * 2 * 4, 0.0);
-    auto md = [N](int x) { return ((x % N) + N) % N; };
     for (const auto& c : P.classes) {
         const dgfs::PairParams& pp = P.pair[c.i * P.s + c.j];
         for (int d = 0; d < c.ndir; ++d) {
@@ -327,44 +325,27 @@ void build_mfma_tables(dgfs_plan& P, std::vector<char>& blob) {
                 for (int fld = 0; fld < 2; ++fld) {
                     const double sgn = fld == 0 ? 1.0 : -1.0, coef = fld == 0 ? c.a : c.b;
                     const size_t t = (size_t(c.dir_offset + d) * nrho + q) * 2 + fld;
-                    std::vector<double> cv[3];
                     for (int ax = 0; ax < 3; ++ax) {
                         const double th = sgn * kPi * pp.rho[q] * coef * sg[ax] / P.L;
-                        cv[ax].resize(N);
-                        for (int dd = 0; dd < N; ++dd) {
+                        for (int j = 0; j < N; ++j) {
+                            const int dd = (N - j) % N;
                             double acc = 0.0;
                             for (int l = -N / 2; l < N / 2; ++l) acc += std::cos(l * (2.0 * kPi * dd / N + th));
-                            cv[ax][dd] = acc / N;
+                            const float v = float(acc / N);
+                            const _Float16 hi = _Float16(v), lo = _Float16(v - float(hi));
+                            uint16_t hb, lb;
+                            std::memcpy(&hb, &hi, 2);
+                            std::memcpy(&lb, &lo, 2);
+                            tab[(t * 3 + ax) * N + j] = uint32_t(hb) | (uint32_t(lb) << 16);
                         }
                         sc[t * 4 + ax] = -std::sin(N * th / 2.0) / N;
                     }
-                    _Float16* base = tab.data() + t * TABH;
-                    auto put = [&](int part, int sub, int lane, int e, double v) {
-                        const float fv = float(v);
-                        const _Float16 hi = _Float16(fv);
-                        base[((size_t(part) * 2 + sub) * 2 + 0) * 512 + lane * 8 + e] = hi;
-                        base[((size_t(part) * 2 + sub) * 2 + 1) * 512 + lane * 8 + e] = _Float16(fv - float(hi));
-                    };
-                    for (int lane = 0; lane < 64; ++lane)
-                        for (int e = 0; e < 8; ++e) {
-                            const int g = lane / 16, m = lane % 16, h = lane / 32, l32 = lane % 32;
-                            // x: B operand of a 16x16x32 tile, k = x' = 8g + e, n = m (x = 2m + chunk)
-                            for (int ch = 0; ch < 2; ++ch) put(0, ch, lane, e, cv[0][md(2 * m + ch - (8 * g + e))]);
-                            for (int s2 = 0; s2 < 2; ++s2) {
-                                // z: B operand of 32x32x16, k = z = 16 s + 8 h + e, n = z_out = l32
-                                put(1, s2, lane, e, cv[2][md(l32 - (16 * s2 + 8 * h + e))]);
-                                // y: A operand of 32x32x16, row y_out = l32, k-slot (s, h, e) = the
-                                // row 8(r/4) + 4h + r%4 (r = 8s + e) of the previous output
-                                const int r = 8 * s2 + e, yk = 8 * (r / 4) + 4 * h + r % 4;
-                                put(2, s2, lane, e, cv[1][md(l32 - yk)]);
-                            }
-                        }
                 }
         }
     }
     P.off_mtab = (blob.size() + 255) & ~size_t(255);
-    blob.resize(P.off_mtab + tab.size() * sizeof(_Float16));
-    std::memcpy(blob.data() + P.off_mtab, tab.data(), tab.size() * sizeof(_Float16));
+    blob.resize(P.off_mtab + tab.size() * sizeof(uint32_t));
+    std::memcpy(blob.data() + P.off_mtab, tab.data(), tab.size() * sizeof(uint32_t));
     push_real<float>(blob, P.off_msc, sc);
 }
 
