@@ -94,6 +94,16 @@ __device__ __forceinline__ void split4(f4v v, h4& hi, h4& lo) {
     lo = __builtin_bit_cast(h4, lp);
 }
 __device__ __forceinline__ h8 ld8(const _Float16* p) { return *reinterpret_cast<const h8*>(p); }
+// v plus v of lane l ^ 32 (l ^ 16): one v_permlane32_swap (v_permlane16_swap) exchanges the
+// halves (rows), so the butterfly sums need no LDS crossbar round trip
+__device__ __forceinline__ float sum_xor32(float v) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float sum_xor16(float v) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
 // 16-byte buffer load: wave-uniform descriptor, lane offset in a VGPR, uniform offset in
 // an SGPR (no per-lane 64-bit addresses)
 __device__ __forceinline__ h8 bld8(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
@@ -265,7 +275,7 @@ __device__ __forceinline__ void alpha_plane(const h8* ah, const h8* al, int cb, 
     float a1 = 0.f;
 #pragma unroll
     for (int r = 0; r < 16; ++r) a1 += (r & 1) ? -dA[r] : dA[r];
-    a1 += __shfl_xor(a1, 32);
+    a1 = sum_xor32(a1);
     if (h == 0) L.Lxy[pb][l32] = a1;
     f16v px = {};
 #pragma unroll
@@ -350,8 +360,7 @@ __device__ __forceinline__ void x_stage(const Args& a, int fs, int tb, int c, Ld
             *reinterpret_cast<h4*>(&GH[o]) = hi;
             *reinterpret_cast<h4*>(&GL[o]) = lo;
         }
-        vpart += __shfl_xor(vpart, 16);
-        vpart += __shfl_xor(vpart, 32);
+        vpart = sum_xor32(sum_xor16(vpart));
         if (g == 0) L.V[bf][mm * VS + y] = vpart;
     }
     const float* aux = prep_aux(a, fs);
@@ -415,7 +424,7 @@ __device__ __forceinline__ void yz_stage(const Args& a, int fs, int tb, int c, L
             d = MF32(tyh[s], bl, d);
             d = MF32(tyl[s], bh, d);
         }
-        ly += __shfl_xor(ly, 32);
+        ly = sum_xor32(ly);
         lyz0 = __builtin_amdgcn_readlane(ly, 0);
         lyz1 = __builtin_amdgcn_readlane(ly, 1);
         if (n < 3) {
@@ -444,7 +453,7 @@ __device__ __forceinline__ void yz_stage(const Args& a, int fs, int tb, int c, L
         float a1 = 0.f;
 #pragma unroll
         for (int r = 0; r < 16; ++r) a1 += (r & 1) ? -d1[r] : d1[r];
-        py[pi] = a1 + __shfl_xor(a1, 32);   // P_y(x_m, z) = sum_y (-1)^y (C_x C_z f)
+        py[pi] = sum_xor32(a1);   // P_y(x_m, z) = sum_y (-1)^y (C_x C_z f)
         d2[pi] = f16v{};
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
