@@ -321,13 +321,8 @@ __device__ __forceinline__ void x_stage(const Args& a, int fs, int tb, int c, Ld
                                         ZYOps& zy) {
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, mm = l & 15;
     const _Float16* fH = prep_h(a, fs);
-    if (nxt_tb >= 0) stage_vectors(a, nxt_tb, L, (pb + 1) % 3);
-    // G1[m][y][z] = sum_x' C_x[2m + c][x'] f[x'][y][z]; 16x16x32 tiles of 16 (y, z)
-    // columns, lane (m = l%16, g = l/16) keeping z = 16 tt + 4 g + r.  The G1 buffer bf was
-    // last read by the field before the previous one.
-    h8 bxh, bxl;
-    op_x(L, pb, c, bxh, bxl);
-    // every operand load of the contraction is issued before the first product
+    // Global reads first, consumed late: the operands of the contraction (all sixteen
+    // loads before the first product), the next field's shift vectors, the field's scalars.
     const __amdgpu_buffer_rsrc_t rf = __builtin_amdgcn_make_buffer_rsrc(const_cast<_Float16*>(fH), 0, 2 * 65536, 0x00020000);
     const int vx = ((4 * w * 32 + mm) * 32 + 8 * g) * 2;   // this lane's bytes within a tile
     h8 xh[8], xl[8];
@@ -337,6 +332,20 @@ __device__ __forceinline__ void x_stage(const Args& a, int fs, int tb, int c, Ld
         xh[t] = bld8(rf, vx, so);
         xl[t] = bld8(rf, vx, so + 65536);
     }
+    const bool stage = nxt_tb >= 0 && tid < TABW;
+    const unsigned vnext = stage ? a.tab[size_t(nxt_tb) * TABW + tid] : 0u;
+    const float* aux = prep_aux(a, fs);
+    const float vaux = (w == 1 && l < 32) ? aux[l] : 0.f;
+    zy.sx = a.sc[4 * tb];
+    zy.sy = a.sc[4 * tb + 1];
+    zy.sz = a.sc[4 * tb + 2];
+    zy.axyz = aux[32];
+    zy.colscale = aux[34];
+    // G1[m][y][z] = sum_x' C_x[2m + c][x'] f[x'][y][z]; 16x16x32 tiles of 16 (y, z)
+    // columns, lane (m = l%16, g = l/16) keeping z = 16 tt + 4 g + r.  The G1 buffer bf was
+    // last read by the field before the previous one.
+    h8 bxh, bxl;
+    op_x(L, pb, c, bxh, bxl);
     f4v X[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) X[t] = MF16(xh[t], bxh, (f4v{}));
@@ -363,13 +372,12 @@ __device__ __forceinline__ void x_stage(const Args& a, int fs, int tb, int c, Ld
         vpart = sum_xor32(sum_xor16(vpart));
         if (g == 0) L.V[bf][mm * VS + y] = vpart;
     }
-    const float* aux = prep_aux(a, fs);
-    if (w == 1 && l < 32) L.V[bf][16 * VS + l] = aux[l];
-    zy.sx = a.sc[4 * tb];
-    zy.sy = a.sc[4 * tb + 1];
-    zy.sz = a.sc[4 * tb + 2];
-    zy.axyz = aux[32];
-    zy.colscale = aux[34];
+    if (w == 1 && l < 32) L.V[bf][16 * VS + l] = vaux;
+    if (stage) {   // the next field's shift vectors, doubled, into buffer (pb + 1) % 3
+        const int ax = tid >> 5, j = tid & 31;
+        L.Cv[(pb + 1) % 3][ax][j] = vnext;
+        L.Cv[(pb + 1) % 3][ax][j + 32] = vnext;
+    }
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         op_z(L, pb, s, zy.bzh[s], zy.bzl[s]);
