@@ -1052,11 +1052,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void r
     constexpr int KZH = N / 2 + 1;
     constexpr int64_t N2 = int64_t(N) * N, N3 = N2 * N, PCH = int64_t(NP) * N * KZH;
     constexpr int64_t PCHF = int64_t(NP) * N2, NREP = N2 * KZH;
-    const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    // Blocks with consecutive indices take the same 256 stored entries for consecutive
+    // node groups, so a block's slice of the kernel-mode tables is read from its XCD's L2
+    // by the node groups that follow, not from memory per group.
     const int64_t ngroups = (a.nb + NB - 1) / NB;
-    if (t >= ngroups * PCH) return;
-    const int e = int(t % PCH);
-    const int b0 = int(t / PCH) * NB;
+    const int64_t ng = int64_t(blockIdx.x) % ngroups;
+    const int64_t eblk = int64_t(blockIdx.x) / ngroups;
+    if (eblk * 256 + threadIdx.x >= PCH) return;
+    const int e = int(eblk * 256 + threadIdx.x);
+    const int b0 = int(ng) * NB;
     const int kz = e % KZH;
     int kxp, ky;
     mirror_paired_row<N, NP>(e / KZH, kxp, ky);
@@ -1354,11 +1358,11 @@ hipError_t run_slice(const dgfs_plan& p, const T* f, T* Q, int nb, void* ws, boo
     const int64_t rthreads = int64_t(nb) * ss.nslots * pch;
     if constexpr (VSS) {
         if (ss.nslots <= 2) {
-            const int64_t th = int64_t((nb + NB2 - 1) / NB2) * pch;
-            radial_vss_kernel<T, N, CH, NB2, 2><<<dim3(unsigned((th + 255) / 256)), dim3(256), 0, st>>>(ra);
+            const int64_t blocks = int64_t((nb + NB2 - 1) / NB2) * ((pch + 255) / 256);
+            radial_vss_kernel<T, N, CH, NB2, 2><<<dim3(unsigned(blocks)), dim3(256), 0, st>>>(ra);
         } else if (ss.nslots <= 4) {
-            const int64_t th = int64_t((nb + NB4 - 1) / NB4) * pch;
-            radial_vss_kernel<T, N, CH, NB4, 4><<<dim3(unsigned((th + 255) / 256)), dim3(256), 0, st>>>(ra);
+            const int64_t blocks = int64_t((nb + NB4 - 1) / NB4) * ((pch + 255) / 256);
+            radial_vss_kernel<T, N, CH, NB4, 4><<<dim3(unsigned(blocks)), dim3(256), 0, st>>>(ra);
         } else {
             radial_kernel<T, N, CH, true><<<dim3(unsigned((rthreads + 255) / 256)), dim3(256), 0, st>>>(ra);
         }

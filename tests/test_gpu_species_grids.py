@@ -55,7 +55,8 @@ def _heavy_light(N):
     return masses, Ls
 
 
-@pytest.mark.parametrize("precision,tol,N,M,nrho", [("f64", 1e-12, 16, 24, 8), ("f32", 1e-5, 24, 12, 12)])
+@pytest.mark.parametrize("precision,tol,N,M,nrho", [("f64", 1e-12, 16, 24, 8), ("f32", 1e-5, 24, 12, 12),
+                                                 ("f32", 1e-5, 32, 6, 8)])
 def test_two_species_two_grids(precision, tol, N, M, nrho):
     """m = (1, 32.75), L_i = 6 sqrt(1/m_i), hard spheres (omega = 0.5): pairs (1,1),
     (1,2), (2,1) on the wide box, (2,2) on the narrow one; summed and per pair.
