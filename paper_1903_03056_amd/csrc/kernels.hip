@@ -139,9 +139,9 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // (32, 2, 0): the matrix-core gain (FP32 VHS plans of the circular form; the others get
 // the first geometry with CZ > 0).
 // N = 36 and 72 are the padded grids of the dealiased form at N = 24 and 48 only.
-constexpr int kTilesF32[][3] = {{16, 1, 1}, {16, 2, 1}, {16, 1, 2}, {24, 3, 1}, {24, 3, 2}, {24, 3, 4},
-                                {32, 2, 0}, {32, 2, 1}, {32, 4, 1}, {32, 4, 2}, {48, 6, 2}, {48, 12, 4}, {48, 12, 2},
-                                {64, 16, 4}, {36, 3, 2}, {72, 24, 4}};
+constexpr int kTilesF32[][3] = {{16, 1, 1}, {16, 2, 1}, {16, 1, 2}, {24, 3, 1}, {24, 3, 2}, {24, 3, 4}, {24, 3, 3},
+                                {24, 1, 1}, {32, 2, 0}, {32, 2, 1}, {32, 4, 1}, {32, 4, 2}, {48, 6, 2}, {48, 12, 4},
+                                {48, 12, 2}, {48, 12, 1}, {48, 12, 3}, {64, 16, 4}, {36, 3, 2}, {72, 24, 4}};
 constexpr int kTilesF64[][3] = {{16, 1, 1}, {24, 3, 2}, {32, 4, 2}, {48, 12, 4}, {64, 32, 8}, {36, 6, 4},
                                 {72, 72, 8}};
 

@@ -22,6 +22,10 @@ hipError_t run_tiles_24(const dgfs_plan& p, const void* f, void* Q, int nb, void
             p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
         case 304: return detail::run_slice<float, 24, 3, 4, false, false, false>(
             p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
+        case 303: return detail::run_slice<float, 24, 3, 3, false, false, false>(
+            p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
+        case 101: return detail::run_slice<float, 24, 1, 1, false, false, false>(
+            p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
         default: return hipErrorInvalidValue;
     }
 }

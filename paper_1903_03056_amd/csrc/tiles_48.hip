@@ -22,6 +22,10 @@ hipError_t run_tiles_48(const dgfs_plan& p, const void* f, void* Q, int nb, void
             p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
         case 1202: return detail::run_slice<float, 48, 12, 2, false, true, false>(
             p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
+        case 1201: return detail::run_slice<float, 48, 12, 1, false, true, false>(
+            p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
+        case 1203: return detail::run_slice<float, 48, 12, 3, false, true, false>(
+            p, static_cast<const float*>(f), static_cast<float*>(Q), nb, ws, pairs, st, ev);
         default: return hipErrorInvalidValue;
     }
 }
