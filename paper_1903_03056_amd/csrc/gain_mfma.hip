@@ -110,6 +110,26 @@ __device__ __forceinline__ h8 bld8(__amdgpu_buffer_rsrc_t r, int voff, int soff)
     return __builtin_bit_cast(h8, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
+// hi | lo << 16 of v in FP16 (hi = f16(v), lo = f16(v - hi)).  Written in plain code: the
+// one-instruction mixed FMA form, with its result read by a matrix product right after,
+// gave results that varied from run to run.
+__device__ __forceinline__ unsigned split_pk(float v) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const _Float16 hi = _Float16(v);
+    const _Float16 lo = _Float16(v - float(hi));
+    return __builtin_bit_cast(unsigned, h2{hi, lo});
+}
+// Operands of a rank-two term u_y b(z) + a(y) u_z of a 32 x 32 tile (u = (-1)^n), one
+// 32x32x16 product over k-slots 0..3: A[y][k] = (u_y, u_y, a_hi(y), a_lo(y)) and B[k][z] =
+// (b_hi(z), b_lo(z), u_z, u_z).  Lane l < 32 supplies y = z = l; uu = (u_l, u_l) in FP16 on
+// those lanes and 0 elsewhere, which zeroes the other lanes' (finite) k-slots.
+__device__ __forceinline__ h8 corr_a(unsigned uu, float av) {
+    return __builtin_bit_cast(h8, u4v{uu, split_pk(av), 0u, 0u});
+}
+__device__ __forceinline__ h8 corr_b(unsigned uu, float bv) {
+    return __builtin_bit_cast(h8, u4v{split_pk(bv), uu, 0u, 0u});
+}
+
 #define MF32(a, b, c) __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0)
 #define MF16(a, b, c) __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0)
 
@@ -249,7 +269,8 @@ __device__ __forceinline__ void op_y(const Lds& L, int cb, int s, h8& hi, h8& lo
     vec_operand(L.Cv[cb][1], (16 * s + 4 * h - l32) & 31, (16 * s + 8 + 4 * h - l32) & 31, hi, lo);
 }
 
-// P_x = C_y C_z a_x in the output layout and L_xy = C_z a_xy of one field (one wavefront).
+// s_x u_x P_x = s_x u_x C_y C_z a_x in the output layout (kx = s_x u_x of the field) and
+// L_xy = C_z a_xy of one field (one wavefront).
 // The a_x plane's A operands of one field (rows y = l%32, z = 16s + 8(l/32) + e).
 __device__ __forceinline__ void load_alpha(const Args& a, int fs, h8* ah, h8* al) {
     const int l = threadIdx.x & 63, h = l >> 5, l32 = l & 31;
@@ -261,7 +282,7 @@ __device__ __forceinline__ void load_alpha(const Args& a, int fs, h8* ah, h8* al
         al[s] = ld8(aL + l32 * 32 + 16 * s + 8 * h);
     }
 }
-__device__ __forceinline__ void alpha_plane(const h8* ah, const h8* al, int cb, Lds& L, int pb) {
+__device__ __forceinline__ void alpha_plane(const h8* ah, const h8* al, int cb, Lds& L, int pb, float kx) {
     const int l = threadIdx.x & 63, h = l >> 5, l32 = l & 31;
     f16v dA = {};
 #pragma unroll
@@ -293,16 +314,16 @@ __device__ __forceinline__ void alpha_plane(const h8* ah, const h8* al, int cb, 
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-        *reinterpret_cast<f4v*>(&L.Px[pb][(j * 64 + l) * 4]) = f4v{px[4 * j], px[4 * j + 1], px[4 * j + 2], px[4 * j + 3]};
+        *reinterpret_cast<f4v*>(&L.Px[pb][(j * 64 + l) * 4]) =
+            f4v{kx * px[4 * j], kx * px[4 * j + 1], kx * px[4 * j + 2], kx * px[4 * j + 3]};
 }
 
-// What the first field of a direction leaves for the second: its contracted values T and
-// the per-plane pieces of its corrections (P_z, L_xz stay in the wavefront's LDS area,
-// P_x and L_xy in their buffer).
+// What the first field of a direction leaves for the second: Re A and the pieces of its
+// Im A (P_z stays in the wavefront's LDS area, s_x u_x P_x in its buffer).
 struct FieldState {
-    f16v T[2];
-    float py[2], lyz[2];
-    float sx, sy, sz, pnt;
+    f16v T[2];       // Re A of the two planes
+    float py[2];     // P_y(x_m, z)
+    float sy, sz, pnt;
 };
 
 // The x-contraction of one field (between two barriers).  fs: (node, species) index of
@@ -386,16 +407,16 @@ __device__ __forceinline__ void x_stage(const Args& a, int fs, int tb, int c, Ld
 }
 
 // The rest of one field, after the barrier that publishes its G1 and V: the wavefront
-// nxt_wave prepares the next field's P_x (nxt_fs), then each wavefront's plane vectors
+// nxt_wave prepares the next field's P_x (input nxt_fs, table nxt_tb), then each wavefront's plane vectors
 // through C_y, its two planes' z- and y-contractions and the corrections.  tb: the
 // field's table, bf: its G1/V buffer (0: first field of the direction, 1: second), pb/pbA:
 // the P_x (and shift-vector) buffers of this field and of the direction's first field.
-// ACC = false keeps the field in st; ACC = true accumulates S += wgt (Re A Re B - Im A Im B)
+// ACC = false keeps the field in st; ACC = true accumulates S += Re A Re B - Im A Im B
 // with A from st and B this field.
 template <bool ACC>
 __device__ __forceinline__ void yz_stage(const Args& a, int fs, int tb, int c, Lds& L, int bf, int pb, int pbA,
-                                         const ZYOps& zy, FieldState& st, int nxt_wave, int nxt_fs, float (*S)[16],
-                                         float wgt) {
+                                         const ZYOps& zy, FieldState& st, int nxt_wave, int nxt_fs, int nxt_tb,
+                                         float (*S)[16]) {
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, h = l >> 5, l32 = l & 31;
     const float sx = zy.sx, sy = zy.sy, sz = zy.sz;
     _Float16* GH = L.G1[bf][0];
@@ -408,7 +429,7 @@ __device__ __forceinline__ void yz_stage(const Args& a, int fs, int tb, int c, L
     if (w == nxt_wave) {
         h8 ah[2], al[2];
         load_alpha(a, nxt_fs, ah, al);
-        alpha_plane(ah, al, (pb + 1) % 3, L, (pb + 1) % 3);
+        alpha_plane(ah, al, (pb + 1) % 3, L, (pb + 1) % 3, a.sc[4 * nxt_tb] * ((c & 1) ? -1.f : 1.f));
     }
     // ---- C_y [v_2w | v_2w+1 | a_xz]: this wavefront's P_z(x_m, y) and L_xz(y); L_yz(x_m)
     float lyz0, lyz1;
@@ -444,9 +465,22 @@ __device__ __forceinline__ void yz_stage(const Args& a, int fs, int tb, int c, L
                     f4v{d[4 * j] * inv, d[4 * j + 1] * inv, d[4 * j + 2] * inv, d[4 * j + 3] * inv};
         }
     }
-    // ---- z- then y-contraction of this wavefront's two planes
-    f16v d2[2];
-    float py[2];
+    // ---- z- then y-contraction of this wavefront's two planes, with the corrections (signs:
+    // u_x = (-1)^c for every plane of the chunk, u_y by the row's parity r%2, u_z by the
+    // lane's parity) as rank-two products on the matrix cores:
+    //   Re A = T + u_y b_re(z) + a_re(y) u_z,   b_re = -(s_x s_y u_x L_xy + s_y s_z u_z L_yz(x_m)),
+    //                                           a_re = -s_x s_z u_x L_xz,
+    //   Im A = s_x u_x P_x + u_y b_im(z) + a_im(y) u_z,   b_im = s_y P_y(x_m) - s_x s_y s_z u_x u_z a_xyz,
+    //                                                     a_im = s_z P_z(x_m).
+    // Re A is formed in each field's own stage (its term starts the y-contraction's
+    // accumulation); the first field keeps it with P_y, s_y and its a_xyz term, and the
+    // second forms both fields' Im A and accumulates S += Re A Re B - Im A Im B (the class
+    // weight is applied once at the end).
+    const float ux = (c & 1) ? -1.f : 1.f, uz = (l & 1) ? -1.f : 1.f;
+    const float pnt = sx * sy * sz * ux * uz * zy.axyz;
+    const unsigned uu = l < 32 ? ((l & 1) ? 0xBC00BC00u : 0x3C003C00u) : 0u;
+    const h8 aRe = corr_a(uu, -sx * sz * ux * L.W[w][bf][2 * VS + l32]);
+    const float lxy = L.Lxy[pb][l32];
 #pragma unroll
     for (int pi = 0; pi < 2; ++pi) {
         f16v d1 = {};
@@ -461,8 +495,8 @@ __device__ __forceinline__ void yz_stage(const Args& a, int fs, int tb, int c, L
         float a1 = 0.f;
 #pragma unroll
         for (int r = 0; r < 16; ++r) a1 += (r & 1) ? -d1[r] : d1[r];
-        py[pi] = sum_xor32(a1);   // P_y(x_m, z) = sum_y (-1)^y (C_x C_z f)
-        d2[pi] = f16v{};
+        const float py = sum_xor32(a1);   // P_y(x_m, z) = sum_y (-1)^y (C_x C_z f)
+        f16v d2 = MF32(aRe, corr_b(uu, -(sx * sy * ux * lxy + sy * sz * uz * (pi == 0 ? lyz0 : lyz1))), (f16v{}));
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             f8v v;
@@ -470,55 +504,36 @@ __device__ __forceinline__ void yz_stage(const Args& a, int fs, int tb, int c, L
             for (int e = 0; e < 8; ++e) v[e] = d1[8 * s + e];
             h8 bh, bl;
             split8(v, bh, bl);
-            d2[pi] = MF32(tyh[s], bh, d2[pi]);
-            d2[pi] = MF32(tyh[s], bl, d2[pi]);
-            d2[pi] = MF32(tyl[s], bh, d2[pi]);
+            d2 = MF32(tyh[s], bh, d2);
+            d2 = MF32(tyh[s], bl, d2);
+            d2 = MF32(tyl[s], bh, d2);
+        }
+        if constexpr (!ACC) {
+            st.T[pi] = d2;
+            st.py[pi] = py;
+        } else {
+            f16v pxB, pxA;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const f4v vb = *reinterpret_cast<const f4v*>(&L.Px[pb][(j * 64 + l) * 4]);
+                const f4v va = *reinterpret_cast<const f4v*>(&L.Px[pbA][(j * 64 + l) * 4]);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    pxB[4 * j + i] = vb[i];
+                    pxA[4 * j + i] = va[i];
+                }
+            }
+            const f16v imB = MF32(corr_a(uu, sz * L.W[w][bf][pi * VS + l32]), corr_b(uu, sy * py - pnt), pxB);
+            const f16v imA =
+                MF32(corr_a(uu, st.sz * L.W[w][bf ^ 1][pi * VS + l32]), corr_b(uu, st.sy * st.py[pi] - st.pnt), pxA);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) S[pi][r] = fmaf(-imA[r], imB[r], fmaf(st.T[pi][r], d2[r], S[pi][r]));
         }
     }
-    // ---- corrections (signs: u_x = (-1)^c for every plane of the chunk, u_y by the row's
-    // parity r%2, u_z by the lane's parity)
-    const float ux = (c & 1) ? -1.f : 1.f, uz = (l & 1) ? -1.f : 1.f;
-    const float pnt = sx * sy * sz * ux * uz * zy.axyz;
     if constexpr (!ACC) {
-        st.T[0] = d2[0];
-        st.T[1] = d2[1];
-        st.py[0] = py[0];
-        st.py[1] = py[1];
-        st.lyz[0] = lyz0;
-        st.lyz[1] = lyz1;
-        st.sx = sx;
         st.sy = sy;
         st.sz = sz;
         st.pnt = pnt;
-    } else {
-        const float cB = sx * sz * ux * uz, K1 = sx * ux, K3 = sz * uz;
-        const float cBA = st.sx * st.sz * ux * uz, K1A = st.sx * ux, K3A = st.sz * uz;
-#pragma unroll
-        for (int pi = 0; pi < 2; ++pi) {
-            const float reE = sx * sy * ux * L.Lxy[pb][l32] + sy * sz * uz * (pi == 0 ? lyz0 : lyz1);
-            const float imE = sy * py[pi] - pnt;
-            const float reEA = st.sx * st.sy * ux * L.Lxy[pbA][l32] + st.sy * st.sz * uz * st.lyz[pi];
-            const float imEA = st.sy * st.py[pi] - st.pnt;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const f4v lxz = *reinterpret_cast<const f4v*>(&L.W[w][bf][2 * VS + 8 * j + 4 * h]);
-                const f4v pz = *reinterpret_cast<const f4v*>(&L.W[w][bf][pi * VS + 8 * j + 4 * h]);
-                const f4v lxzA = *reinterpret_cast<const f4v*>(&L.W[w][bf ^ 1][2 * VS + 8 * j + 4 * h]);
-                const f4v pzA = *reinterpret_cast<const f4v*>(&L.W[w][bf ^ 1][pi * VS + 8 * j + 4 * h]);
-                const f4v px = *reinterpret_cast<const f4v*>(&L.Px[pb][(j * 64 + l) * 4]);
-                const f4v pxA = *reinterpret_cast<const f4v*>(&L.Px[pbA][(j * 64 + l) * 4]);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = 4 * j + i;
-                    const float sgn = (i & 1) ? -1.f : 1.f;
-                    const float rv = d2[pi][r] - sgn * reE - cB * lxz[i];
-                    const float iv = K1 * px[i] + sgn * imE + K3 * pz[i];
-                    const float rA = st.T[pi][r] - sgn * reEA - cBA * lxzA[i];
-                    const float iA = K1A * pxA[i] + sgn * imEA + K3A * pzA[i];
-                    S[pi][r] = fmaf(wgt, fmaf(-iA, iv, rA * rv), S[pi][r]);
-                }
-            }
-        }
     }
 }
 
@@ -548,7 +563,6 @@ __global__ __launch_bounds__(NT) void gain_kernel(Args a) {
     const int cl = item / a.nrho;
     const int ci = a.cls[4 * cl], cj = a.cls[4 * cl + 1], ndir = a.cls[4 * cl + 2], doff = a.cls[4 * cl + 3];
     const int fA = b * a.s + ci, fB = b * a.s + cj;
-    const float wgt = a.wdir[cl] * prep_aux(a, fA)[33] * prep_aux(a, fB)[33];
     const int w = threadIdx.x >> 6;
     auto tab = [&](int d, int fld) { return ((doff + d) * a.nrho + q) * 2 + fld; };
     float S[2][16];
@@ -566,7 +580,7 @@ __global__ __launch_bounds__(NT) void gain_kernel(Args a) {
     if (w == 0) {
         h8 ah[2], al[2];
         load_alpha(a, fA, ah, al);
-        alpha_plane(ah, al, 0, L, 0);
+        alpha_plane(ah, al, 0, L, 0, a.sc[4 * tab(0, 0)] * ((c & 1) ? -1.f : 1.f));
     }
     const int nf = 2 * ndir;
 #pragma unroll 1
@@ -576,12 +590,15 @@ __global__ __launch_bounds__(NT) void gain_kernel(Args a) {
         ZYOps zy;
         x_stage(a, fA, tab(d, 0), c, L, 0, k % 3, tab(d, 1), zy);
         __syncthreads();
-        yz_stage<false>(a, fA, tab(d, 0), c, L, 0, k % 3, 0, zy, st, (k + 1) % 8, fB, S, 0.f);
+        yz_stage<false>(a, fA, tab(d, 0), c, L, 0, k % 3, 0, zy, st, (k + 1) % 8, fB, tab(d, 1), S);
         const bool more = k + 2 < nf;
         x_stage(a, fB, tab(d, 1), c, L, 1, (k + 1) % 3, more ? tab(d + 1, 0) : -1, zy);
         __syncthreads();
-        yz_stage<true>(a, fB, tab(d, 1), c, L, 1, (k + 1) % 3, k % 3, zy, st, more ? (k + 2) % 8 : -1, fA, S, wgt);
+        yz_stage<true>(a, fB, tab(d, 1), c, L, 1, (k + 1) % 3, k % 3, zy, st, more ? (k + 2) % 8 : -1, fA,
+                       more ? tab(d + 1, 0) : 0, S);
     }
+    // the class weight and the undoing of both inputs' scales
+    const float wgt = a.wdir[cl] * prep_aux(a, fA)[33] * prep_aux(a, fB)[33];
     __syncthreads();  // every wavefront is done with the contraction buffers
     // S_q to LDS as rows (plane m, y) of z values, then the forward transform of gain_kernel
     using K = GainK<float, N, 2, 1>;
@@ -592,7 +609,7 @@ __global__ __launch_bounds__(NT) void gain_kernel(Args a) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int y = 8 * (r / 4) + 4 * h + r % 4;
-                sm.buf[((2 * w + pi) * N + y) * K::ROW + (l & 31)] = cx<float>{S[pi][r], 0.f};
+                sm.buf[((2 * w + pi) * N + y) * K::ROW + (l & 31)] = cx<float>{wgt * S[pi][r], 0.f};
             }
     }
     __syncthreads();
