@@ -208,45 +208,45 @@ __global__ __launch_bounds__(256) void prep_kernel(Args a) {
 
 // ------------------------------------------------------------------ gain kernel
 struct Lds {
+    // The small arrays first: their addresses stay below 64 KB, within the reach of the
+    // LDS instructions' immediate offsets.
+    unsigned Cv[3][3][2][64];      // shift vectors r of three fields in flight, [axis][hi, lo]: word o
+                                   // holds r(o mod 32) and r((o + 1) mod 32) in FP16
+    float Lxy[3][32];
+    float Px[3][4 * 64 * 4];       // s_x u_x P_x in the output layout, three fields in flight
+    float W[8][2][3 * VS];         // per wavefront and field: C_y v_2w, C_y v_2w+1, C_y a_xz
+    float V[2][17 * VS];           // [buffer]: v_m(y) = sum_z (-1)^z (C_x f)(x_m, y, z), then a_xz(y)
     _Float16 G1[2][2][16 * PST];   // x-contracted field [buffer][hi, lo][plane]: rows y, 16-byte
                                    // blocks of z rotated by y/4 (conflict-free row reads)
-    float V[2][17 * VS];           // [buffer]: v_m(y) = sum_z (-1)^z (C_x f)(x_m, y, z), then a_xz(y)
-    float W[8][2][3 * VS];         // per wavefront and field: C_y v_2w, C_y v_2w+1, C_y a_xz
-    float Px[3][4 * 64 * 4];       // P_x in the output layout, three fields in flight
-    float Lxy[3][32];
-    unsigned Cv[3][3][64];         // shift vectors r of three fields in flight, [axis][j mod 32] twice
 };
 static_assert(sizeof(Lds) <= 160 * 1024, "LDS");
 
 __device__ __forceinline__ int g1off(int m, int y, int blk) { return m * PST + y * 32 + ((blk + (y >> 2)) & 3) * 8; }
 
+// Thread t < 96 of a table (axis t / 32, j = t % 32) holds v = r(j) and vn = r(j + 1) as
+// hi | lo << 16 and writes the words j and j + 32 of its axis in buffer cb.
+__device__ __forceinline__ void put_vectors(Lds& L, int cb, int t, unsigned v, unsigned vn) {
+    const int ax = t >> 5, j = t & 31;
+    const unsigned wh = __builtin_amdgcn_perm(vn, v, 0x05040100u);   // hi(r(j)) | hi(r(j + 1)) << 16
+    const unsigned wl = __builtin_amdgcn_perm(vn, v, 0x07060302u);
+    L.Cv[cb][ax][0][j] = wh;
+    L.Cv[cb][ax][0][j + 32] = wh;
+    L.Cv[cb][ax][1][j] = wl;
+    L.Cv[cb][ax][1][j + 32] = wl;
+}
+__device__ __forceinline__ int next_entry(int t) { return (t & ~31) | ((t + 1) & 31); }
 // Write the shift vectors of table tb into LDS buffer cb (threads 0..95).
 __device__ __forceinline__ void stage_vectors(const Args& a, int tb, Lds& L, int cb) {
     const int t = threadIdx.x;
-    if (t < TABW) {
-        const unsigned v = a.tab[size_t(tb) * TABW + t];
-        const int ax = t >> 5, j = t & 31;
-        L.Cv[cb][ax][j] = v;
-        L.Cv[cb][ax][j + 32] = v;
-    }
+    if (t < TABW) put_vectors(L, cb, t, a.tab[size_t(tb) * TABW + t], a.tab[size_t(tb) * TABW + next_entry(t)]);
 }
-// An operand of 8 consecutive matrix entries r(o), ..., r(o + 7) (o + e < 64) of one axis,
-// unpacked to FP16 hi and lo.  Two runs of four: r(o1..o1+3), r(o2..o2+3).
-__device__ __forceinline__ void vec_operand(const unsigned* v, int o1, int o2, h8& hi, h8& lo) {
-    unsigned w[8];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        w[e] = v[o1 + e];
-        w[4 + e] = v[o2 + e];
-    }
-    u4v hp, lp;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        hp[k] = __builtin_amdgcn_perm(w[2 * k + 1], w[2 * k], 0x05040100u);   // low halves
-        lp[k] = __builtin_amdgcn_perm(w[2 * k + 1], w[2 * k], 0x07060302u);   // high halves
-    }
-    hi = __builtin_bit_cast(h8, hp);
-    lo = __builtin_bit_cast(h8, lp);
+// An operand of 8 matrix entries of one axis in FP16 hi and lo: two runs of four,
+// r(o1..o1+3) and r(o2..o2+3) (0 <= o1, o2 < 32), two words each.
+__device__ __forceinline__ void vec_operand(const unsigned (*v)[64], int o1, int o2, h8& hi, h8& lo) {
+    const unsigned* p1 = &v[0][o1];
+    const unsigned* p2 = &v[0][o2];
+    hi = __builtin_bit_cast(h8, u4v{p1[0], p1[2], p2[0], p2[2]});
+    lo = __builtin_bit_cast(h8, u4v{p1[64], p1[66], p2[64], p2[66]});
 }
 // B operand of the x-contraction (16x16x32, k = x' = 8g + e, n = m): C_x[2m + c][x'] =
 // r_x((x' - 2m - c) mod N).
@@ -355,6 +355,7 @@ __device__ __forceinline__ void x_stage(const Args& a, int fs, int tb, int c, Ld
     }
     const bool stage = nxt_tb >= 0 && tid < TABW;
     const unsigned vnext = stage ? a.tab[size_t(nxt_tb) * TABW + tid] : 0u;
+    const unsigned vnext1 = stage ? a.tab[size_t(nxt_tb) * TABW + next_entry(tid)] : 0u;
     const float* aux = prep_aux(a, fs);
     const float vaux = (w == 1 && l < 32) ? aux[l] : 0.f;
     zy.sx = a.sc[4 * tb];
@@ -394,11 +395,7 @@ __device__ __forceinline__ void x_stage(const Args& a, int fs, int tb, int c, Ld
         if (g == 0) L.V[bf][mm * VS + y] = vpart;
     }
     if (w == 1 && l < 32) L.V[bf][16 * VS + l] = vaux;
-    if (stage) {   // the next field's shift vectors, doubled, into buffer (pb + 1) % 3
-        const int ax = tid >> 5, j = tid & 31;
-        L.Cv[(pb + 1) % 3][ax][j] = vnext;
-        L.Cv[(pb + 1) % 3][ax][j + 32] = vnext;
-    }
+    if (stage) put_vectors(L, (pb + 1) % 3, tid, vnext, vnext1);   // the next field's shift vectors
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         op_z(L, pb, s, zy.bzh[s], zy.bzl[s]);
