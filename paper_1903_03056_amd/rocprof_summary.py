@@ -115,7 +115,7 @@ if __name__ == "__main__":
     t, f, w, p = sys.argv[1:5]
     cmds = {
         "trace": "rocprofv3 --kernel-trace --stats -d DIR -o trace --output-format csv -- "
-                 "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-plain --no-extra",
+                 "python3 bench.py --steps 20 --warmup 2 --no-cpu-baseline --no-plain --no-extra",
         "fetch": "rocprofv3 --pmc FETCH_SIZE -d DIR -o fetch --output-format csv -- "
                  "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-plain --no-extra --copy-probe",
         "write": "rocprofv3 --pmc WRITE_SIZE -d DIR -o write --output-format csv -- "
