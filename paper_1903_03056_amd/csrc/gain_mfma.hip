@@ -15,7 +15,9 @@
 // with T = C_x C_y C_z f, P_x = C_y C_z a_x, P_y = C_x C_z a_y, P_z = C_x C_y a_z,
 // L_xy = C_z a_xy, L_xz = C_y a_xz, L_yz = C_x a_yz, where a_E is f summed with the signs
 // (-1)^n over the axes in E.  T is three dense contractions (the MFMAs); the other terms
-// are planes, lines and a scalar.
+// are planes, lines and a scalar.  On one x-plane every term but T and s_x u_x P_x is a
+// line in y times u_z or u_y times a line in z, so each of Re A and Im A gets its
+// corrections from one more 32x32x16 product over four k-slots (corr_a, corr_b).
 //
 // Arithmetic: every MFMA operand is split as hi + lo in FP16 (hi = f16(v), lo = f16(v -
 // hi)) and a product is hi*hi + hi*lo + lo*hi, accumulated in FP32 (about 2^-22 of each
@@ -404,8 +406,9 @@ __device__ __forceinline__ void x_stage(const Args& a, int fs, int tb, int c, Ld
 }
 
 // The rest of one field, after the barrier that publishes its G1 and V: the wavefront
-// nxt_wave prepares the next field's P_x (input nxt_fs, table nxt_tb), then each wavefront's plane vectors
-// through C_y, its two planes' z- and y-contractions and the corrections.  tb: the
+// nxt_wave prepares the next field's P_x (input nxt_fs, table nxt_tb), then each
+// wavefront's plane vectors go through C_y, its two planes through the z- and
+// y-contractions and the corrections.  tb: the
 // field's table, bf: its G1/V buffer (0: first field of the direction, 1: second), pb/pbA:
 // the P_x (and shift-vector) buffers of this field and of the direction's first field.
 // ACC = false keeps the field in st; ACC = true accumulates S += Re A Re B - Im A Im B
