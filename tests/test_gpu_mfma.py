@@ -134,3 +134,19 @@ def test_matrix_core_rejected_where_it_does_not_apply():
     err = _rel(Q[0], ref)
     print(f"VSS default geometry: {err:.3e}", flush=True)
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("noise", [0.5, 1.0])
+def test_matrix_core_rough_inputs(noise):
+    """Grid noise of half and all of the peak (clipped at zero): the alternating sums behind
+    the correction terms are then far from zero.  Both the matrix-core and the FFT
+    geometry against the oracle, each within the FP32 bound."""
+    _require_gpu()
+    print(f"[case] matrix-core rough input, noise {noise}", flush=True)
+    f = I.draw_bimaxwellian_batch(np.random.default_rng(31), 1, 2, N, L, MASSES, noise=noise).astype(np.float32)
+    ref = OS.collide(f[0].astype(np.float64), OS.vhs_problem(MASSES, OMEGA, L, N, M, NRHO))
+    errs = {}
+    for tile in ((2, 0), (2, 1)):
+        errs[tile] = _rel(_collide(_plan(tile), f)[0], ref)
+    print(f"matrix cores {errs[(2, 0)]:.3e}, FFT {errs[(2, 1)]:.3e}", flush=True)
+    assert errs[(2, 0)] <= 1e-5 and errs[(2, 1)] <= 1e-5
