@@ -481,36 +481,59 @@ __device__ __forceinline__ void yz_stage(const Args& a, int fs, int tb, int c, L
     const unsigned uu = l < 32 ? ((l & 1) ? 0xBC00BC00u : 0x3C003C00u) : 0u;
     const h8 aRe = corr_a(uu, -sx * sz * ux * L.W[w][bf][2 * VS + l32]);
     const float lxy = L.Lxy[pb][l32];
+    // z-contraction of the two planes, their chains interleaved
+    f16v d1[2] = {f16v{}, f16v{}};
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        h8 ah[2], al[2];
+#pragma unroll
+        for (int pi = 0; pi < 2; ++pi) {
+            const int o = g1off(2 * w + pi, l32, 2 * s + h);
+            ah[pi] = ld8(GH + o);
+            al[pi] = ld8(GL + o);
+        }
+#pragma unroll
+        for (int pi = 0; pi < 2; ++pi) d1[pi] = MF32(ah[pi], bzh[s], d1[pi]);
+#pragma unroll
+        for (int pi = 0; pi < 2; ++pi) d1[pi] = MF32(ah[pi], bzl[s], d1[pi]);
+#pragma unroll
+        for (int pi = 0; pi < 2; ++pi) d1[pi] = MF32(al[pi], bzh[s], d1[pi]);
+    }
+    float py[2];
 #pragma unroll
     for (int pi = 0; pi < 2; ++pi) {
-        f16v d1 = {};
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int o = g1off(2 * w + pi, l32, 2 * s + h);
-            const h8 ah = ld8(GH + o), al = ld8(GL + o);
-            d1 = MF32(ah, bzh[s], d1);
-            d1 = MF32(ah, bzl[s], d1);
-            d1 = MF32(al, bzh[s], d1);
-        }
         float a1 = 0.f;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) a1 += (r & 1) ? -d1[r] : d1[r];
-        const float py = sum_xor32(a1);   // P_y(x_m, z) = sum_y (-1)^y (C_x C_z f)
-        f16v d2 = MF32(aRe, corr_b(uu, -(sx * sy * ux * lxy + sy * sz * uz * (pi == 0 ? lyz0 : lyz1))), (f16v{}));
+        for (int r = 0; r < 16; ++r) a1 += (r & 1) ? -d1[pi][r] : d1[pi][r];
+        py[pi] = sum_xor32(a1);   // P_y(x_m, z) = sum_y (-1)^y (C_x C_z f)
+    }
+    // y-contraction, interleaved likewise (Re A's rank-two term starts each chain)
+    f16v d2[2];
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
+    for (int pi = 0; pi < 2; ++pi)
+        d2[pi] = MF32(aRe, corr_b(uu, -(sx * sy * ux * lxy + sy * sz * uz * (pi == 0 ? lyz0 : lyz1))), (f16v{}));
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        h8 bh[2], bl[2];
+#pragma unroll
+        for (int pi = 0; pi < 2; ++pi) {
             f8v v;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = d1[8 * s + e];
-            h8 bh, bl;
-            split8(v, bh, bl);
-            d2 = MF32(tyh[s], bh, d2);
-            d2 = MF32(tyh[s], bl, d2);
-            d2 = MF32(tyl[s], bh, d2);
+            for (int e = 0; e < 8; ++e) v[e] = d1[pi][8 * s + e];
+            split8(v, bh[pi], bl[pi]);
         }
+#pragma unroll
+        for (int pi = 0; pi < 2; ++pi) d2[pi] = MF32(tyh[s], bh[pi], d2[pi]);
+#pragma unroll
+        for (int pi = 0; pi < 2; ++pi) d2[pi] = MF32(tyh[s], bl[pi], d2[pi]);
+#pragma unroll
+        for (int pi = 0; pi < 2; ++pi) d2[pi] = MF32(tyl[s], bh[pi], d2[pi]);
+    }
+#pragma unroll
+    for (int pi = 0; pi < 2; ++pi) {
         if constexpr (!ACC) {
-            st.T[pi] = d2;
-            st.py[pi] = py;
+            st.T[pi] = d2[pi];
+            st.py[pi] = py[pi];
         } else {
             f16v pxB, pxA;
 #pragma unroll
@@ -523,11 +546,11 @@ __device__ __forceinline__ void yz_stage(const Args& a, int fs, int tb, int c, L
                     pxA[4 * j + i] = va[i];
                 }
             }
-            const f16v imB = MF32(corr_a(uu, sz * L.W[w][bf][pi * VS + l32]), corr_b(uu, sy * py - pnt), pxB);
+            const f16v imB = MF32(corr_a(uu, sz * L.W[w][bf][pi * VS + l32]), corr_b(uu, sy * py[pi] - pnt), pxB);
             const f16v imA =
                 MF32(corr_a(uu, st.sz * L.W[w][bf ^ 1][pi * VS + l32]), corr_b(uu, st.sy * st.py[pi] - st.pnt), pxA);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) S[pi][r] = fmaf(-imA[r], imB[r], fmaf(st.T[pi][r], d2[r], S[pi][r]));
+            for (int r = 0; r < 16; ++r) S[pi][r] = fmaf(-imA[r], imB[r], fmaf(st.T[pi][r], d2[pi][r], S[pi][r]));
         }
     }
     if constexpr (!ACC) {
