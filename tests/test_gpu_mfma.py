@@ -150,3 +150,15 @@ def test_matrix_core_rough_inputs(noise):
         errs[tile] = _rel(_collide(_plan(tile), f)[0], ref)
     print(f"matrix cores {errs[(2, 0)]:.3e}, FFT {errs[(2, 1)]:.3e}", flush=True)
     assert errs[(2, 0)] <= 1e-5 and errs[(2, 1)] <= 1e-5
+
+
+def test_matrix_core_repeats_bit_for_bit():
+    """The same batch three times in a row gives the same bits: an operand read by a matrix
+    product before the instruction that forms it has landed would show up here as
+    rounding-level differences between runs."""
+    _require_gpu()
+    print("[case] matrix-core run-to-run", flush=True)
+    plan = _plan()
+    f = I.draw_bimaxwellian_batch(np.random.default_rng(26), 37, 2, N, L, MASSES, noise=1e-2).astype(np.float32)
+    runs = [_collide(plan, f) for _ in range(3)]
+    assert np.array_equal(runs[0], runs[1]) and np.array_equal(runs[0], runs[2])
