@@ -136,23 +136,24 @@ __device__ __forceinline__ h8 corr_b(unsigned uu, float bv) {
 #define MF16(a, b, c) __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0)
 
 // ------------------------------------------------------------------ input preparation
-// One workgroup per (node, species): the scale 2^k, f hi/lo transposed to [col = (y, z)][x]
+// One workgroup of 1024 threads per (node, species): the scale 2^k, f hi/lo transposed to [col = (y, z)][x]
 // (the A operand of the x-contraction), a_x = sum_x (-1)^x f as hi/lo [y][z], then
 // a_xz(y) = sum_z (-1)^z a_x(y, z) with its own scale, a_xyz, and 2^-k.
 // aux: [0, 32) a_xz(y) * 2^-j, [32] a_xyz, [33] 2^-k, [34] 2^j.
-__global__ __launch_bounds__(256) void prep_kernel(Args a) {
+constexpr int PT = 1024;   // threads of the preparation kernel: one per (y, z) column
+__global__ __launch_bounds__(PT) void prep_kernel(Args a) {
     const int fs = blockIdx.x, tid = threadIdx.x;
     const float* f = a.f + size_t(fs) * (N * N * N);
     _Float16* out = reinterpret_cast<_Float16*>(reinterpret_cast<char*>(a.prep) + size_t(fs) * mfma_prep_bytes);
     float* aux = reinterpret_cast<float*>(out + PREPH);
-    __shared__ float red[256];
+    __shared__ float red[PT];
     __shared__ float ax[N * N];
     __shared__ float axz[N];
     float mx = 0.f;
-    for (int i = tid; i < N * N * N; i += 256) mx = fmaxf(mx, fabsf(f[i]));
+    for (int i = tid; i < N * N * N; i += PT) mx = fmaxf(mx, fabsf(f[i]));
     red[tid] = mx;
     __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
+    for (int k = PT / 2; k > 0; k >>= 1) {
         if (tid < k) red[tid] = fmaxf(red[tid], red[tid + k]);
         __syncthreads();
     }
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(256) void prep_kernel(Args a) {
     if (M > 0.f && M <= 3.0e38f) (void)frexpf(M, &e);   // M = m 2^e, m in [0.5, 1)
     const int k = (M > 0.f && M <= 3.0e38f) ? max(-120, min(120, 8 - e)) : 0;
     const float scale = ldexpf(1.f, k);
-    for (int col = tid; col < N * N; col += 256) {
+    for (int col = tid; col < N * N; col += PT) {
         const int y = col >> 5, z = col & 31;
         float acc = 0.f;
 #pragma unroll
@@ -656,7 +657,7 @@ hipError_t launch_gain_mfma32(const dgfs_plan& p, const float* f, cx<float>* P, 
     a.ncls = int(p.classes.size());
     a.nrho = p.nrho;
     a.nb = nb;
-    mfma::prep_kernel<<<dim3(unsigned(int64_t(nb) * p.s)), dim3(256), 0, st>>>(a);
+    mfma::prep_kernel<<<dim3(unsigned(int64_t(nb) * p.s)), dim3(mfma::PT), 0, st>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t ipn = int64_t(a.ncls) * p.nrho * 2;
