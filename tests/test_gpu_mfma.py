@@ -162,3 +162,19 @@ def test_matrix_core_repeats_bit_for_bit():
     f = I.draw_bimaxwellian_batch(np.random.default_rng(26), 37, 2, N, L, MASSES, noise=1e-2).astype(np.float32)
     runs = [_collide(plan, f) for _ in range(3)]
     assert np.array_equal(runs[0], runs[1]) and np.array_equal(runs[0], runs[2])
+
+
+def test_matrix_core_non_antipodal_design():
+    """The 24-point design (not antipodal: one class per ordered pair, 24 directions each)
+    with two radial points, against the oracle."""
+    _require_gpu()
+    print("[case] matrix-core M=24", flush=True)
+    from paper_1903_03056_amd import CollisionPlan
+    f = I.draw_bimaxwellian_batch(np.random.default_rng(27), 2, 2, N, L, MASSES, noise=1e-2).astype(np.float32)
+    plan = CollisionPlan(MASSES, N, L, 24, 2, omega=OMEGA, precision="f32", tile=(2, 0))
+    Q = _collide(plan, f)
+    prob = OS.vhs_problem(MASSES, OMEGA, L, N, 24, 2)
+    for b in range(2):
+        err = _rel(Q[b], OS.collide(f[b].astype(np.float64), prob))
+        print(f"node {b}: {err:.3e}", flush=True)
+        assert err <= 1e-5
