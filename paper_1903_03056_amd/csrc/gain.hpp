@@ -805,12 +805,37 @@ __device__ __forceinline__ void vss_accumulate(cx<A>& acc, const cx<T> h[2], con
     }
 }
 
-// Plane and index of mode k in the V array (k has a component at the Nyquist index).
+// Slot of entry (r, c) of a Nyquist plane in the mirror-paired layout: each entry and
+// its plane mirror ((N - r) % N, (N - c) % N) fill one aligned pair of slots (rows r and
+// N - r interleaved; in the self-mirror rows 0 and N/2, columns c and N - c), and the four
+// entries that are their own mirror take the last two slots of those two rows.
 template <int N>
-__device__ __forceinline__ int vplane_index(int kx, int ky, int kz) {
-    if (kz == N / 2) return 0 * N * N + kx * N + ky;
-    if (ky == N / 2) return 1 * N * N + kx * N + kz;
-    return 2 * N * N + ky * N + kz;
+__device__ __forceinline__ int vpair_slot(int r, int c) {
+    constexpr int H = N / 2;
+    if (r != 0 && r != H) {
+        const int lo = r < H ? r : N - r;
+        return 2 * N * lo + 2 * (r < H ? c : (N - c) % N) + (r < H ? 0 : 1);
+    }
+    const int base = r == 0 ? 0 : N;
+    if (c != 0 && c != H) return base + 2 * ((c < H ? c : N - c) - 1) + (c < H ? 0 : 1);
+    return base + N - 2 + (c == 0 ? 0 : 1);
+}
+// Slot of mode k (with a component at the Nyquist index) in the three mirror-paired
+// planes: [k_x][k_y] where k_z = N/2, else [k_x][k_z] where k_y = N/2, else [k_y][k_z].
+template <int N>
+__device__ __forceinline__ int vplane_slot(int kx, int ky, int kz) {
+    if (kz == N / 2) return vpair_slot<N>(kx, ky);
+    if (ky == N / 2) return N * N + vpair_slot<N>(kx, kz);
+    return 2 * N * N + vpair_slot<N>(ky, kz);
+}
+// W at k and at its plane mirror from the aligned pair holding them.
+template <typename T, int N>
+__device__ __forceinline__ void w_pair(const cx<T>* Vb, int kx, int ky, int kz, cx<T>& w, cx<T>& wm) {
+    const int sl = vplane_slot<N>(kx, ky, kz);
+    const cx<T> p0 = Vb[sl & ~1], p1 = Vb[sl | 1];
+    const bool self = (kx == 0 || kx == N / 2) + (ky == 0 || ky == N / 2) + (kz == 0 || kz == N / 2) == 3;
+    w = (sl & 1) ? p1 : p0;
+    wm = self ? w : ((sl & 1) ? p0 : p1);
 }
 
 // W = DFT(Im S_0 + i Im S_1) on the three Nyquist planes from the plane sums: one block
@@ -852,15 +877,10 @@ __global__ __launch_bounds__(3 * N) void nyquist_dft_kernel(const T* __restrict_
         for (int k = 0; k < N; ++k) Ls[plane][t][k] = x[k];
     }
     __syncthreads();
-    cx<T>* out = V + it * int64_t(3 * N2) + plane * N2;
-    for (int row = 0; row < N; ++row) out[row * N + t] = Ls[plane][row][t];
+    cx<T>* out = V + it * int64_t(3 * N2) + plane * N2;   // mirror-paired slots (vpair_slot)
+    for (int row = 0; row < N; ++row) out[vpair_slot<N>(row, t)] = Ls[plane][row][t];
 }
 
-// The plane-mirror of mode index k in the W array (same plane, other two indices negated).
-template <int N>
-__device__ __forceinline__ int vplane_mirror(int kx, int ky, int kz) {
-    return vplane_index<N>((N - kx) % N, (N - ky) % N, kz == N / 2 ? kz : (N - kz) % N);
-}
 
 // V_0 and V_1 at k from W at k and at its plane mirror.
 template <typename T>
@@ -878,7 +898,8 @@ struct RadialArgs {
     const T* F;         // [nftab][nrho][K2]  w_q F(|k|, rho_q) / N^3
     const cx<T>* Fv;    // VSS: [nftab][nrho][2 directions][2][N][N][N/2+1]  F_H, F_A: the Hermitian and
                         //      anti-Hermitian parts (in the index sense) of w_q w_sigma F / N^3
-    const cx<T>* V;     // VSS: [nb][ncls][nrho][3][N^2]  DFT(Im S_0 + i Im S_1) on the planes k_z, k_y, k_x = N/2
+    const cx<T>* V;     // VSS: [nb][ncls][nrho][3][N^2]  DFT(Im S_0 + i Im S_1) on the planes k_z, k_y, k_x = N/2,
+                        //      each plane in the mirror-paired slots of vpair_slot
     const T* G;         // [ngtab][K2]        G-(|k|)
     const cx<T>* tw;    // [N][CH]  e^{-2 pi i kx c / N}
     const int* slots;   // [nslots][5]
@@ -959,8 +980,11 @@ __global__ __launch_bounds__(256) void radial_kernel(RadialArgs<T> a) {
                     }
                     const bool nyq = kx == N / 2 || ky == N / 2 || kz == N / 2;
                     if (nyq)
-                        split_w<T>(Vb[int64_t(q) * (3 * N2) + vplane_index<N>(kx, ky, kz)],
-                                   Vb[int64_t(q) * (3 * N2) + vplane_mirror<N>(kx, ky, kz)], v);
+                    {
+                        cx<T> w, wm;
+                        w_pair<T, N>(Vb + int64_t(q) * (3 * N2), kx, ky, kz, w, wm);
+                        split_w<T>(w, wm, v);
+                    }
                     vss_accumulate<T>(acc[j], h, fa, 0.5 * (double(Z.x) + double(Zm.x)),
                                       0.5 * (double(Z.y) - double(Zm.y)), 0.5 * (double(Z.y) + double(Zm.y)),
                                       0.5 * (double(Zm.x) - double(Z.x)), nyq, v);
@@ -1078,10 +1102,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void r
 
     constexpr int N2I = N * N;
     bool nyq[CH];
+    int wi[CH];   // the aligned pair holding W at k and at its plane mirror (pair 0 off the planes)
+    bool wodd[CH], wself[CH];
     bool nyq_any = false;
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
-        nyq[j] = kxp + j * NP == N / 2 || ky == N / 2 || kz == N / 2;
+        const int kx = kxp + j * NP;
+        nyq[j] = kx == N / 2 || ky == N / 2 || kz == N / 2;
+        const int sl = nyq[j] ? vplane_slot<N>(kx, ky, kz) : 0;
+        wi[j] = sl & ~1;
+        wodd[j] = (sl & 1) != 0;
+        wself[j] = (kx == 0 || kx == N / 2) + (ky == 0 || ky == N / 2) + (kz == 0 || kz == N / 2) == 3;
         nyq_any = nyq_any || nyq[j];
     }
     for (int cl = 0; cl < a.ncls; ++cl) {
@@ -1119,11 +1150,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void r
                 if (b >= a.nb) break;
                 const cx<T>* Pb = a.P + ((int64_t(b) * a.ncls + cl) * a.nrho + q) * (CH * PCHF);
                 const cx<T>* Vb = a.V + ((int64_t(b) * a.ncls + cl) * a.nrho + q) * (3 * N2I);
-                cx<T> pc[CH], pm[CH];
+                cx<T> pc[CH], pm[CH], w0[CH], w1[CH];
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
                     pc[c] = Pb[c * PCHF + eP];
                     pm[c] = Pb[c * PCHF + ePm];
+                }
+                // the Nyquist-plane values, read with the partials (every lane, the
+                // lanes off the planes all at one address) rather than after them
+#pragma unroll
+                for (int j = 0; j < CH; ++j) {
+                    w0[j] = Vb[wi[j]];
+                    w1[j] = Vb[wi[j] + 1];
                 }
 #pragma unroll
                 for (int j = 0; j < CH; ++j) {
@@ -1135,7 +1173,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void r
                         cmac(Zm, a.tw[kxm * CH + c], pm[c]);
                     }
                     cx<T> v[2];
-                    if (nyq[j]) split_w<T>(Vb[vplane_index<N>(kx, ky, kz)], Vb[vplane_mirror<N>(kx, ky, kz)], v);
+                    if (nyq[j]) {
+                        const cx<T> w = wodd[j] ? w1[j] : w0[j];
+                        split_w<T>(w, wself[j] ? w : (wodd[j] ? w0[j] : w1[j]), v);
+                    }
                     const T u0x = T(0.5) * (Z.x + Zm.x), u0y = T(0.5) * (Z.y - Zm.y);
                     const T u1x = T(0.5) * (Z.y + Zm.y), u1y = T(0.5) * (Zm.x - Z.x);
 #pragma unroll
