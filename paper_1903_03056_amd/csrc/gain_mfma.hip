@@ -40,7 +40,6 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 typedef float f8v __attribute__((ext_vector_type(8)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef unsigned u4v __attribute__((ext_vector_type(4)));
-typedef unsigned u2v __attribute__((ext_vector_type(2)));
 
 constexpr int N = 32;
 constexpr int NT = 512;
@@ -71,29 +70,15 @@ __device__ __forceinline__ const float* prep_aux(const Args& a, int fs) {
                                           size_t(PREPH) * 2);
 }
 
-// v = hi + lo, hi = f16(v), lo = f16(v - hi): the residual is formed and rounded by one
-// mixed-precision FMA per value (v_fma_mixlo/hi_f16 each write one half of the result).
-__device__ __forceinline__ unsigned mix_lo2(unsigned hp, float v0, float v1) {
-    unsigned r;
-    asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(hp), "v"(v0));
-    asm("v_fma_mixhi_f16 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(r) : "v"(hp), "v"(v1));
-    return r;
-}
+// v = hi + lo with hi = f16(v) and lo = f16(v - hi); v - hi is exact in FP32, so lo takes
+// one rounding.
 __device__ __forceinline__ void split8(f8v v, h8& hi, h8& lo) {
     hi = __builtin_convertvector(v, h8);
-    const u4v hp = __builtin_bit_cast(u4v, hi);
-    u4v lp;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) lp[k] = mix_lo2(hp[k], v[2 * k], v[2 * k + 1]);
-    lo = __builtin_bit_cast(h8, lp);
+    lo = __builtin_convertvector(v - __builtin_convertvector(hi, f8v), h8);
 }
 __device__ __forceinline__ void split4(f4v v, h4& hi, h4& lo) {
     hi = __builtin_convertvector(v, h4);
-    const u2v hp = __builtin_bit_cast(u2v, hi);
-    u2v lp;
-#pragma unroll
-    for (int k = 0; k < 2; ++k) lp[k] = mix_lo2(hp[k], v[2 * k], v[2 * k + 1]);
-    lo = __builtin_bit_cast(h4, lp);
+    lo = __builtin_convertvector(v - __builtin_convertvector(hi, f4v), h4);
 }
 __device__ __forceinline__ h8 ld8(const _Float16* p) { return *reinterpret_cast<const h8*>(p); }
 // v plus v of lane l ^ 32 (l ^ 16): one v_permlane32_swap (v_permlane16_swap) exchanges the
@@ -112,9 +97,7 @@ __device__ __forceinline__ h8 bld8(__amdgpu_buffer_rsrc_t r, int voff, int soff)
     return __builtin_bit_cast(h8, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
-// hi | lo << 16 of v in FP16 (hi = f16(v), lo = f16(v - hi)).  Written in plain code: the
-// one-instruction mixed FMA form, with its result read by a matrix product right after,
-// gave results that varied from run to run.
+// hi | lo << 16 of v in FP16 (hi = f16(v), lo = f16(v - hi)).
 __device__ __forceinline__ unsigned split_pk(float v) {
     typedef _Float16 h2 __attribute__((ext_vector_type(2)));
     const _Float16 hi = _Float16(v);
