@@ -30,6 +30,11 @@ FLAGS = [
 ]
 
 
+# per-source additions: the N = 48 FFT gain kernel runs about 1 % faster under the
+# scheduler's max-ILP strategy (measured; the same flag slows the matrix-core kernel)
+EXTRA_FLAGS = {"tiles_48.hip": ["-mllvm", "--amdgpu-sched-strategy=max-ilp"]}
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc"):
         if cand and os.path.exists(cand):
@@ -39,7 +44,8 @@ def hipcc() -> str:
 
 def _compile(src: str, resource_usage: bool):
     obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *FLAGS, "-I", os.path.join(ROOT, "include"), "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *FLAGS, *EXTRA_FLAGS.get(src, []), "-I", os.path.join(ROOT, "include"), "-c",
+           os.path.join(CSRC, src), "-o", obj]
     if resource_usage:
         cmd.append("-Rpass-analysis=kernel-resource-usage")
     res = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True)
