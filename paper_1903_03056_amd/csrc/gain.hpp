@@ -383,6 +383,50 @@ __device__ __forceinline__ void x_pencil(__amdgpu_buffer_rsrc_t rs, int vo, int 
     fft<NP, +1>(y);
 }
 
+// x_pencil for two fields with the same spectrum (a like class: A and B both shift f^i)
+// on a paired slot: every input is loaded once and enters both sums, each with its own
+// phase table; each output takes the same operations in the same order as x_pencil's.
+template <typename T, int N, int CH, bool PIPE>
+__device__ __forceinline__ void x_pencil2(__amdgpu_buffer_rsrc_t rs, int vo, const cx<T>* __restrict__ kxa,
+                                          const cx<T>* __restrict__ kxb, cx<T>* ya, cx<T>* yb) {
+    constexpr int NP = N / CH;
+    constexpr int RS = N * N * int(sizeof(cx<T>));
+#pragma unroll
+    for (int l = 0; l < NP; ++l) ya[l] = yb[l] = cx<T>{T(0), T(0)};
+    if constexpr (PIPE) {
+        cx<T> nxt[NP];
+#pragma unroll
+        for (int l = 0; l < NP; ++l) nxt[l] = bload<T>(rs, vo, l * RS);
+#pragma unroll 1
+        for (int t = 0; t < CH; ++t) {
+            cx<T> cur[NP];
+#pragma unroll
+            for (int l = 0; l < NP; ++l) cur[l] = nxt[l];
+            if (t + 1 < CH) {
+#pragma unroll
+                for (int l = 0; l < NP; ++l) nxt[l] = bload<T>(rs, vo, (l + (t + 1) * NP) * RS);
+            }
+#pragma unroll
+            for (int l = 0; l < NP; ++l) {
+                cmac(ya[l], cur[l], kxa[l + t * NP]);
+                cmac(yb[l], cur[l], kxb[l + t * NP]);
+            }
+        }
+    } else {
+#pragma unroll 1
+        for (int t = 0; t < CH; ++t) {
+#pragma unroll
+            for (int l = 0; l < NP; ++l) {
+                const cx<T> v = bload<T>(rs, vo, (l + t * NP) * RS);
+                cmac(ya[l], v, kxa[l + t * NP]);
+                cmac(yb[l], v, kxb[l + t * NP]);
+            }
+        }
+    }
+    fft<NP, +1>(ya);
+    fft<NP, +1>(yb);
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> pack_ab(cx<T> a, cx<T> b) { return cx<T>{a.x - b.y, a.y + b.x}; }          // a + i b
 template <typename T>
@@ -427,6 +471,7 @@ __device__ __forceinline__ void packed_direction(const cx<T>* __restrict__ fa, c
     cx<T>* LY = buf + K::LDS;           // [NP][N+1]: line l_y = N/2, indexed [x][l_z]
     cx<T>* LZ = LY + NP * (N + 1);      // [NP][N+1]: line l_z = N/2, indexed [x][l_y]
     const __amdgpu_buffer_rsrc_t rsa = field_rsrc<T>(fa, N * RS), rsb = field_rsrc<T>(fb, N * RS);
+    const bool same = fa == fb;   // a like class: both fields shift one spectrum
     const int tid = threadIdx.x;
     cx<T> pl[2][2];  // plane values of the slot's two pencils, per round
 
@@ -441,8 +486,12 @@ __device__ __forceinline__ void packed_direction(const cx<T>* __restrict__ fa, c
         const int vo2 = (SELF && !paired) ? vo + H * ES : vo;
         const T mk = (SELF && !paired) ? T(1) : T(0);
         cx<T> ya[NP], yb[NP];
-        x_pencil<T, N, CH, PIPE>(rsa, vo, vo2, mk, two, kxa, ya);
-        x_pencil<T, N, CH, PIPE>(rsb, vo, vo2, mk, two, kxb, yb);
+        if (same && !two) {
+            x_pencil2<T, N, CH, PIPE>(rsa, vo, kxa, kxb, ya, yb);
+        } else {
+            x_pencil<T, N, CH, PIPE>(rsa, vo, vo2, mk, two, kxa, ya);
+            x_pencil<T, N, CH, PIPE>(rsb, vo, vo2, mk, two, kxb, yb);
+        }
         const cx<T> fna = bload<T>(rsa, vo, H * RS), fnb = bload<T>(rsb, vo, H * RS);
         cx<T> p0, p1;
         if (paired) {
