@@ -172,6 +172,43 @@ __device__ __forceinline__ bool pencil_slot(int slot, int& ly, int& lz) {
     return false;
 }
 
+// sum_t of the chunk terms in[l + t NP] * kx[l + t NP] for one pencil, with two load
+// buffers in turn: the next batch of NP loads is in flight while the other is consumed,
+// and no register copies between batches.  U tables (one per output) share the loads.
+// (The packed N = 48 form's x-pass; at N = 32 the one-field x-pass keeps its rotating
+// buffer, which compiles without spills there.)
+template <typename T, int NP, int CH, int U>
+__device__ __forceinline__ void x_sum_pipe(__amdgpu_buffer_rsrc_t rs, int vo, int rs_stride,
+                                           const cx<T>* const (&kx)[U], cx<T>* const (&y)[U]) {
+    cx<T> b0[NP], b1[NP];
+    auto load = [&](cx<T>* b, int t) {
+#pragma unroll
+        for (int l = 0; l < NP; ++l) b[l] = bload<T>(rs, vo, (l + t * NP) * rs_stride);
+    };
+    auto use = [&](const cx<T>* b, int t) {
+#pragma unroll
+        for (int l = 0; l < NP; ++l)
+#pragma unroll
+            for (int u = 0; u < U; ++u) cmac(y[u][l], b[l], kx[u][l + t * NP]);
+    };
+    load(b0, 0);
+    int t = 0;
+#pragma unroll 1
+    for (; t + 2 < CH; t += 2) {
+        load(b1, t + 1);
+        use(b0, t);
+        load(b0, t + 2);
+        use(b1, t + 1);
+    }
+    if constexpr (CH % 2 == 0) {
+        load(b1, CH - 1);
+        use(b0, CH - 2);
+        use(b1, CH - 1);
+    } else {
+        use(b0, CH - 1);
+    }
+}
+
 // Chunk c of IDFT(f_hat * phase) for one shifted field: out[j] at (x = CH m + c,
 // y = r, z = CZ j + cz).  The x-pass reads the spectrum from global memory (coalesced
 // over (l_y, l_z)) and keeps only the chunk's x-outputs: the CH strided input
@@ -358,21 +395,9 @@ __device__ __forceinline__ void x_pencil(__amdgpu_buffer_rsrc_t rs, int vo, int 
                 cmac(y[l], cx<T>{a[l].x - mk * b[l].y, a[l].y + mk * b[l].x}, kxt[l + t * NP]);
         }
     } else if constexpr (PIPE) {
-        cx<T> nxt[NP];
-#pragma unroll
-        for (int l = 0; l < NP; ++l) nxt[l] = bload<T>(rs, vo, l * RS);
-#pragma unroll 1
-        for (int t = 0; t < CH; ++t) {
-            cx<T> cur[NP];
-#pragma unroll
-            for (int l = 0; l < NP; ++l) cur[l] = nxt[l];
-            if (t + 1 < CH) {
-#pragma unroll
-                for (int l = 0; l < NP; ++l) nxt[l] = bload<T>(rs, vo, (l + (t + 1) * NP) * RS);
-            }
-#pragma unroll
-            for (int l = 0; l < NP; ++l) cmac(y[l], cur[l], kxt[l + t * NP]);
-        }
+        const cx<T>* const kx1[1] = {kxt};
+        cx<T>* const y1[1] = {y};
+        x_sum_pipe<T, NP, CH, 1>(rs, vo, RS, kx1, y1);
     } else {
 #pragma unroll 1
         for (int t = 0; t < CH; ++t) {
@@ -394,24 +419,9 @@ __device__ __forceinline__ void x_pencil2(__amdgpu_buffer_rsrc_t rs, int vo, con
 #pragma unroll
     for (int l = 0; l < NP; ++l) ya[l] = yb[l] = cx<T>{T(0), T(0)};
     if constexpr (PIPE) {
-        cx<T> nxt[NP];
-#pragma unroll
-        for (int l = 0; l < NP; ++l) nxt[l] = bload<T>(rs, vo, l * RS);
-#pragma unroll 1
-        for (int t = 0; t < CH; ++t) {
-            cx<T> cur[NP];
-#pragma unroll
-            for (int l = 0; l < NP; ++l) cur[l] = nxt[l];
-            if (t + 1 < CH) {
-#pragma unroll
-                for (int l = 0; l < NP; ++l) nxt[l] = bload<T>(rs, vo, (l + (t + 1) * NP) * RS);
-            }
-#pragma unroll
-            for (int l = 0; l < NP; ++l) {
-                cmac(ya[l], cur[l], kxa[l + t * NP]);
-                cmac(yb[l], cur[l], kxb[l + t * NP]);
-            }
-        }
+        const cx<T>* const kx2[2] = {kxa, kxb};
+        cx<T>* const y2[2] = {ya, yb};
+        x_sum_pipe<T, NP, CH, 2>(rs, vo, RS, kx2, y2);
     } else {
 #pragma unroll 1
         for (int t = 0; t < CH; ++t) {
