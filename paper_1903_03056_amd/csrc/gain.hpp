@@ -437,6 +437,51 @@ __device__ __forceinline__ void x_pencil2(__amdgpu_buffer_rsrc_t rs, int vo, con
     fft<NP, +1>(yb);
 }
 
+// The x-passes of two fields with different spectra (an unlike class) interleaved: both
+// fields' loads of a batch are in flight together, each field in two buffers in turn.
+template <typename T, int N, int CH>
+__device__ __forceinline__ void x_pencil_ab(__amdgpu_buffer_rsrc_t rsa, __amdgpu_buffer_rsrc_t rsb, int vo,
+                                            const cx<T>* __restrict__ kxa, const cx<T>* __restrict__ kxb,
+                                            cx<T>* ya, cx<T>* yb) {
+    constexpr int NP = N / CH;
+    constexpr int RS = N * N * int(sizeof(cx<T>));
+#pragma unroll
+    for (int l = 0; l < NP; ++l) ya[l] = yb[l] = cx<T>{T(0), T(0)};
+    cx<T> a0[NP], a1[NP], b0[NP], b1[NP];
+    auto load = [&](cx<T>* a, cx<T>* b, int t) {
+#pragma unroll
+        for (int l = 0; l < NP; ++l) {
+            a[l] = bload<T>(rsa, vo, (l + t * NP) * RS);
+            b[l] = bload<T>(rsb, vo, (l + t * NP) * RS);
+        }
+    };
+    auto use = [&](const cx<T>* a, const cx<T>* b, int t) {
+#pragma unroll
+        for (int l = 0; l < NP; ++l) {
+            cmac(ya[l], a[l], kxa[l + t * NP]);
+            cmac(yb[l], b[l], kxb[l + t * NP]);
+        }
+    };
+    load(a0, b0, 0);
+    int t = 0;
+#pragma unroll 1
+    for (; t + 2 < CH; t += 2) {
+        load(a1, b1, t + 1);
+        use(a0, b0, t);
+        load(a0, b0, t + 2);
+        use(a1, b1, t + 1);
+    }
+    if constexpr (CH % 2 == 0) {
+        load(a1, b1, CH - 1);
+        use(a0, b0, CH - 2);
+        use(a1, b1, CH - 1);
+    } else {
+        use(a0, b0, CH - 1);
+    }
+    fft<NP, +1>(ya);
+    fft<NP, +1>(yb);
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> pack_ab(cx<T> a, cx<T> b) { return cx<T>{a.x - b.y, a.y + b.x}; }          // a + i b
 template <typename T>
@@ -498,6 +543,8 @@ __device__ __forceinline__ void packed_direction(const cx<T>* __restrict__ fa, c
         cx<T> ya[NP], yb[NP];
         if (same && !two) {
             x_pencil2<T, N, CH, PIPE>(rsa, vo, kxa, kxb, ya, yb);
+        } else if (PIPE && !two) {
+            x_pencil_ab<T, N, CH>(rsa, rsb, vo, kxa, kxb, ya, yb);
         } else {
             x_pencil<T, N, CH, PIPE>(rsa, vo, vo2, mk, two, kxa, ya);
             x_pencil<T, N, CH, PIPE>(rsb, vo, vo2, mk, two, kxb, yb);
